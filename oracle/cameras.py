@@ -1,0 +1,106 @@
+"""Viewer and light cameras, float64 torch (oracle; test infrastructure only).
+
+The shadow map is parameterized over a plane of rays from the light through a
+projective camera map L (Sec. 3).  Light cameras follow the supplementary
+renderer details: a directional light uses an orthographic camera placed far
+outside the scene facing the origin; a spot light uses a perspective camera at
+its position with a configurable field of view.  A point light here uses the
+same perspective construction (one shadow map per light, Sec. 5).
+
+Matrices are textbook OpenGL-style (right-handed, camera looking down -z,
+clip -> NDC in [-1,1]^3).  The matrix the discrete raster uses is the float32
+rounding of the float64 matrix; the continuous part uses the same rounded
+values while autograd differentiates the float64 construction
+("straight-through" rounding), so both parts see one light camera.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+D = torch.float64
+
+
+def _t(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), dtype=D)
+
+
+def normalize(v):
+    return v / torch.sqrt((v * v).sum(-1, keepdim=True))
+
+
+def look_at(eye, target, up):
+    f = normalize(target - eye)
+    s = normalize(torch.linalg.cross(f, up))
+    u = torch.linalg.cross(s, f)
+    z = torch.zeros((), dtype=D)
+    o = torch.ones((), dtype=D)
+    return torch.stack([
+        torch.cat([s, -(s * eye).sum().reshape(1)]),
+        torch.cat([u, -(u * eye).sum().reshape(1)]),
+        torch.cat([-f, (f * eye).sum().reshape(1)]),
+        torch.stack([z, z, z, o]),
+    ])
+
+
+def perspective(fov_deg, aspect, near, far):
+    t = 1.0 / math.tan(math.radians(fov_deg) / 2.0)
+    return _t([[t / aspect, 0, 0, 0],
+               [0, t, 0, 0],
+               [0, 0, (far + near) / (near - far), 2 * far * near / (near - far)],
+               [0, 0, -1, 0]])
+
+
+def orthographic(half, near, far):
+    return _t([[1.0 / half, 0, 0, 0],
+               [0, 1.0 / half, 0, 0],
+               [0, 0, -2.0 / (far - near), -(far + near) / (far - near)],
+               [0, 0, 0, 1]])
+
+
+# When True, matrices and light-frame vectors carry their float32-rounded
+# values (the precision the renderer works in) while autograd differentiates
+# the float64 construction.  Finite-difference checks switch it off: the
+# rounding is a staircase in the light parameters that central differences
+# with tiny steps would see as noise.
+ROUND_TO_F32 = True
+
+
+def round_f32(x):
+    """float32 rounding of a float64 tensor, differentiated as the identity."""
+    if not ROUND_TO_F32:
+        return x
+    return x + (x.detach().to(torch.float32).to(D) - x.detach())
+
+
+def camera_matrix(cam):
+    """Viewer camera VP (float64), aspect = width / height."""
+    V = look_at(_t(cam.eye), _t(cam.target), _t(cam.up))
+    P = perspective(cam.fov_deg, cam.width / cam.height, cam.near, cam.far)
+    return round_f32(P @ V)
+
+
+def light_frame(light, param):
+    """Light camera and the quantities the lookup needs, from the light's
+    differentiable parameter (position, or travel direction for directional).
+
+    Returns dict with M (4x4 view-projection), pos (point/spot: position;
+    directional: camera eye on the plane distances are measured from), w
+    (directional: unit travel direction; spot: cone axis), far, kind,
+    cos_half (spot cone)."""
+    if light.kind == 'directional':
+        w = normalize(param)
+        eye = -light.dir_distance * w
+        V = look_at(eye, torch.zeros(3, dtype=D), _t(light.up))
+        P = orthographic(light.ortho_half, light.near, light.far)
+        return dict(M=round_f32(P @ V), pos=round_f32(eye), w=round_f32(w), far=light.far,
+                    kind='directional', cos_half=None)
+    tgt = _t(light.target)
+    V = look_at(param, tgt, _t(light.up))
+    P = perspective(light.fov_deg, 1.0, light.near, light.far)
+    axis = normalize(tgt - param)
+    cos_half = math.cos(math.radians(light.fov_deg) / 2.0) if light.kind == 'spot' else None
+    return dict(M=round_f32(P @ V), pos=param, w=round_f32(axis), far=light.far, kind=light.kind,
+                cos_half=cos_half)
