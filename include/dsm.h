@@ -1,0 +1,263 @@
+/*
+ * dsm.h -- C ABI of the MI355X (gfx950) library for differentiable
+ * pre-filtered shadow mapping (Worchel & Alexa, "Differentiable Shadow
+ * Mapping for Efficient Inverse Graphics", CVPR 2023).
+ *
+ * The library renders Lambert-shaded images whose shadows come from
+ * variance shadow maps (Sec. 3: moments of a filtered shadow map and the
+ * one-sided Chebyshev bound; Alg. 1 RenderShadowMap, Alg. 2
+ * ComputeVisibility) and computes the reverse-mode gradient of a loss on
+ * those images with respect to vertex positions, light parameters and
+ * albedo (Sec. 4, derivatives of the moments and of the visibility).
+ * Borders of primitives are antialiased in both the light and the camera
+ * view; that smoothing is what carries gradients across silhouettes and
+ * shadow borders (Sec. 4; Sec. 5, optimization without smoothed shadow map).
+ *
+ * Conventions for every call:
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors); every other pointer is host memory read during the call only.
+ *  - Arrays are dense row-major, float32 unless stated; vertices [V,3],
+ *    faces [F,3] int32 with scene-local vertex indices, images [H,W,C].
+ *  - All device work is enqueued on `stream` (a hipStream_t; NULL = the
+ *    default stream).  Calls return once the work is enqueued; outputs are
+ *    valid after the stream reaches that point.  A plan must not be used
+ *    from two streams at once.
+ *  - Every call returns a dsm_status.  Arguments are validated on the host
+ *    before anything is enqueued; on an error nothing is enqueued and
+ *    outputs are left untouched.  No exception or abort crosses the ABI.
+ *  - Gradient outputs are overwritten, never accumulated.
+ *  - Thread safety: distinct plans may be used from distinct host threads.
+ */
+#ifndef DSM_H
+#define DSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSM_ABI_VERSION 1
+
+typedef enum {
+    DSM_OK = 0,
+    DSM_ERR_INVALID_ARG = 1,          /* a null pointer, size or index out of range       */
+    DSM_ERR_OUT_OF_MEMORY = 2,        /* plan-owned device memory could not be allocated  */
+    DSM_ERR_WORKSPACE_TOO_SMALL = 3,  /* caller workspace smaller than the plan requires  */
+    DSM_ERR_UNSUPPORTED = 4,          /* valid request this build does not implement      */
+    DSM_ERR_NO_DEVICE = 5,            /* no HIP device                                    */
+    DSM_ERR_HIP = 6,                  /* a HIP runtime call failed                         */
+    DSM_ERR_DEVICE_FAULT = 7          /* device-side invariant violated (see dsm_get_stats) */
+} dsm_status;
+
+enum { DSM_LIGHT_DIRECTIONAL = 0, DSM_LIGHT_POINT = 1, DSM_LIGHT_SPOT = 2 };
+enum { DSM_FILTER_BOX = 0, DSM_FILTER_GAUSSIAN = 1 };
+
+/* Limits checked by every entry point. */
+#define DSM_MAX_RESOLUTION 8192      /* shadow-map side and camera width/height        */
+#define DSM_MAX_KERNEL 31            /* odd filter size k, 1 <= k <= 31, and k <= S    */
+#define DSM_MAX_LIGHTS_PER_RENDER 16
+
+typedef void *dsm_stream;            /* hipStream_t */
+typedef struct dsm_plan dsm_plan;
+
+/*
+ * One light and its shadow map (Sec. 3 light model; one map per light,
+ * Sec. 5).  The light camera is built on the device from the differentiable
+ * light parameter (position for point/spot lights, travel direction for
+ * directional lights) passed to dsm_forward:
+ *   directional: orthographic, eye = -dir_distance * w (w = unit travel
+ *                direction) looking at the origin, half-extent ortho_half;
+ *                distance d(x) = (x - eye) . w, a plane outside the scene;
+ *   point, spot: perspective at the position looking at `target`, vertical
+ *                field of view fov_deg, aspect 1; d(x) = |x - position|.
+ *                A spot light lights only the cone of half-angle fov_deg/2
+ *                around its axis (hard mask, no gradient through it).
+ * Depths are stored as z = d / zfar.  `k` is the odd filter size of the
+ * moment filter (box or Gaussian with std. dev. sigma in texels; sigma <= 0
+ * means (k-1)/3).  min_variance floors sigma^2 = m2 - m1^2.
+ */
+typedef struct {
+    int32_t type;          /* DSM_LIGHT_*                                   */
+    int32_t scene;         /* scene index the light shadows                 */
+    float target[3];       /* point/spot look-at target                     */
+    float up[3];           /* up vector of the light camera                 */
+    float fov_deg;         /* point/spot field of view (spot: cone angle)   */
+    float dir_distance;    /* directional: eye distance from the origin     */
+    float ortho_half;      /* directional: orthographic half-extent         */
+    float znear, zfar;
+    float intensity;
+    int32_t resolution;    /* shadow-map side S                             */
+    int32_t filter;        /* DSM_FILTER_*                                  */
+    int32_t k;
+    float sigma;
+    float min_variance;
+    int32_t antialias;     /* smooth the light view at primitive borders    */
+} dsm_light_desc;
+
+/* A perspective viewer camera (fixed; no gradient). */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float fov_deg;         /* vertical field of view, aspect = width/height */
+    float znear, zfar;
+    int32_t width, height;
+    int32_t scene;
+} dsm_camera_desc;
+
+/* One rendered image: a camera and a set of lights whose Lambert terms are
+ * summed (deferred shading over any number of lights). */
+typedef struct {
+    int32_t camera;        /* index into cameras                           */
+    int32_t light_begin;   /* range into render_light_list                 */
+    int32_t light_count;
+} dsm_render_desc;
+
+/*
+ * A batch: scenes of uneven size concatenated (CSR offsets), each with any
+ * number of lights and cameras, and renders pairing them.  Everything here is
+ * host memory, copied by dsm_plan_create.
+ */
+typedef struct {
+    int32_t num_scenes;
+    const int32_t *vert_offsets;       /* [num_scenes+1] into the vertex array        */
+    const int32_t *face_offsets;       /* [num_scenes+1] into the face array          */
+    const int32_t *faces;              /* [F_total,3] scene-local vertex indices      */
+    const int32_t *pose_counts;        /* [num_scenes] or NULL: posed vertex prefix   */
+    const float *pose_centers;         /* [num_scenes,3] or NULL                      */
+    int32_t num_lights;
+    const dsm_light_desc *lights;
+    int32_t num_cameras;
+    const dsm_camera_desc *cameras;
+    int32_t num_renders;
+    const dsm_render_desc *renders;
+    const int32_t *render_light_list;  /* light indices referenced by the renders     */
+    int32_t channels;                  /* 1 or 3 colour channels                      */
+    int32_t camera_antialias;          /* smooth the shaded images at borders         */
+} dsm_batch_desc;
+
+/* Sizes a caller needs, filled by dsm_plan_info. */
+typedef struct {
+    int64_t total_vertices;
+    int64_t total_faces;
+    int64_t image_floats;        /* sum over renders of H*W*C                          */
+    int64_t saved_bytes;         /* forward state kept for the backward pass           */
+    int64_t scratch_bytes;       /* temporaries of one forward or backward call        */
+    int64_t map_floats;          /* sum over lights of 2*S*S                           */
+    int32_t tile_size;           /* raster tile side in pixels                         */
+    int32_t bin_capacity_scale;  /* bin capacity = scale * (triangles + tiles) / 4     */
+} dsm_plan_info;
+
+/* Counters of the last forward pass (device-side, read back on demand). */
+typedef struct {
+    uint64_t culled_triangles;   /* dropped by the w > 0 / near / guard-band tests     */
+    uint64_t binned_pairs;       /* (triangle, tile) pairs requested                    */
+    uint64_t overflow_triangles; /* rasterized by the overflow path (bins full)         */
+    uint64_t bad_indices;        /* faces referencing vertices outside their scene      */
+} dsm_stats;
+
+const char *dsm_version(void);
+const char *dsm_status_string(dsm_status status);
+
+/*
+ * Build a plan for a batch: validates the description, uploads faces, builds
+ * the edge adjacency used for silhouette tests, lays out every buffer.
+ * tile_size: raster tile side (8, 16 or 32; 0 = library default 16);
+ * bin_capacity_scale: the tile bins hold bin_capacity_scale * (triangles +
+ * tiles) / 4 (triangle, tile) pairs over all views (1..1024; 0 = default 32).
+ * Triangles whose pairs do not fit are rasterized by a slower overflow path
+ * with identical results.
+ * The plan owns only mesh-static device data (faces, adjacency, layout).
+ */
+dsm_status dsm_plan_create(const dsm_batch_desc *desc, int32_t tile_size, int32_t bin_capacity_scale,
+                           dsm_plan **out_plan);
+dsm_status dsm_plan_info_get(const dsm_plan *plan, dsm_plan_info *out);
+void dsm_plan_destroy(dsm_plan *plan);
+
+/*
+ * Forward pass (Alg. 1 for every light, then Alg. 2 and Lambert shading for
+ * every render).
+ *   verts_dev        [V_total,3] world-space vertex positions
+ *   light_params_dev [L,3] position (point/spot) or travel direction (dir.)
+ *   albedo_dev       [F_total,C] per-face albedo
+ *   saved_dev        saved_bytes of caller memory, written here, read by
+ *                    dsm_backward (keep it alive and unmodified in between)
+ *   scratch_dev      scratch_bytes of caller memory
+ *   images_dev       [image_floats]: render r's [H,W,C] image at the offset
+ *                    sum_{r'<r} H W C
+ */
+dsm_status dsm_forward(dsm_plan *plan, const float *verts_dev, const float *light_params_dev,
+                       const float *albedo_dev, void *saved_dev, size_t saved_bytes,
+                       void *scratch_dev, size_t scratch_bytes, float *images_dev, dsm_stream stream);
+
+/*
+ * Reverse pass of dsm_forward for upstream image gradient grad_images_dev
+ * (same layout as images).  Outputs (overwritten):
+ *   grad_verts_dev        [V_total,3]
+ *   grad_light_params_dev [L,3]
+ *   grad_albedo_dev       [F_total,C] or NULL
+ * verts/light_params/albedo/saved must be those of the matching forward.
+ */
+dsm_status dsm_backward(dsm_plan *plan, const float *verts_dev, const float *light_params_dev,
+                        const float *albedo_dev, const void *saved_dev, size_t saved_bytes,
+                        void *scratch_dev, size_t scratch_bytes, const float *grad_images_dev,
+                        float *grad_verts_dev, float *grad_light_params_dev, float *grad_albedo_dev,
+                        dsm_stream stream);
+
+/*
+ * Rigid pose of the first pose_counts[s] vertices of each scene:
+ * world = R(r) v + center + t, pose [num_scenes,6] = (axis-angle r, t).
+ * Vertices past the prefix are copied unchanged.  pose_backward turns the
+ * world-vertex gradient into [num_scenes,6] pose gradients (overwritten).
+ */
+dsm_status dsm_pose_forward(dsm_plan *plan, const float *local_verts_dev, const float *poses_dev,
+                            float *world_verts_dev, dsm_stream stream);
+dsm_status dsm_pose_backward(dsm_plan *plan, const float *local_verts_dev, const float *poses_dev,
+                             const float *grad_world_dev, float *grad_poses_dev, dsm_stream stream);
+
+/*
+ * Capture one forward + backward (+ pose forward/backward when poses_dev is
+ * not NULL) with the given pointers into a HIP graph owned by the plan, and
+ * replay it with dsm_graph_launch.  Pointers must stay valid and unchanged
+ * for as long as the graph is replayed; a new capture replaces the old one.
+ */
+dsm_status dsm_graph_capture(dsm_plan *plan, const float *local_verts_dev, const float *poses_dev,
+                             float *verts_dev, const float *light_params_dev, const float *albedo_dev,
+                             void *saved_dev, size_t saved_bytes, void *scratch_dev, size_t scratch_bytes,
+                             float *images_dev, const float *grad_images_dev, float *grad_verts_dev,
+                             float *grad_light_params_dev, float *grad_albedo_dev, float *grad_poses_dev,
+                             dsm_stream stream);
+dsm_status dsm_graph_launch(dsm_plan *plan, dsm_stream stream);
+
+/*
+ * Stage outputs of the last forward, copied out of `saved` (parity checks).
+ *  dsm_get_view_keys: 64-bit depth|triangle keys of view v (lights first,
+ *      then cameras; ~0 = background) -> [H,W] uint64.
+ *  dsm_get_light_maps: which = 0 unsmoothed (z, z^2), 1 smoothed, 2 filtered
+ *      moments (m1, m2) -> [2,S,S].  which = 1 needs scratch of the forward
+ *      still intact (it is not part of the saved state).
+ *  dsm_get_render_image0: shaded image of render r before border smoothing.
+ */
+dsm_status dsm_get_view_keys(const dsm_plan *plan, const void *saved_dev, int32_t view,
+                             uint64_t *keys_dev, dsm_stream stream);
+dsm_status dsm_get_light_maps(const dsm_plan *plan, const void *saved_dev, const void *scratch_dev,
+                              int32_t light, int32_t which, float *out_dev, dsm_stream stream);
+dsm_status dsm_get_render_image0(const dsm_plan *plan, const void *saved_dev, int32_t render,
+                                 float *out_dev, dsm_stream stream);
+/* Counters of the last forward; synchronizes `stream`. */
+dsm_status dsm_get_stats(const dsm_plan *plan, const void *scratch_dev, dsm_stats *out, dsm_stream stream);
+
+/*
+ * Moment filter on its own (Eq. moment1 and moment2: m = G f~ for both
+ * channels): n_maps maps of 2 channels, [n_maps,2,S,S].  adjoint = 0 applies
+ * G (horizontal then vertical pass, clamp-to-edge); adjoint = 1 applies G^T
+ * (the transpose, with out-of-range taps folded onto the border texels).
+ * in_dev and out_dev must not overlap.
+ */
+dsm_status dsm_filter_moments(int32_t S, int32_t n_maps, int32_t filter, int32_t k, float sigma,
+                              const float *in_dev, float *out_dev, int32_t adjoint, dsm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSM_H */

@@ -1,0 +1,570 @@
+// C ABI: plans, forward / backward passes, pose, graphs, stage getters.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "dsm_internal.h"
+#include "frames.h"
+#include "plan.h"
+
+using namespace dsm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+__global__ void zero_kernel(unsigned *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+hipError_t zero_async(void *p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned *)p, n);
+    return hipGetLastError();
+}
+
+template <class T>
+dsm_status upload(T **dst, const T *src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return DSM_OK;
+    if (hipMalloc((void **)dst, n * sizeof(T)) != hipSuccess) return DSM_ERR_OUT_OF_MEMORY;
+    if (hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return DSM_ERR_HIP;
+    return DSM_OK;
+}
+
+bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Edge adjacency of one scene: for face f and original edge k (opposite
+// vertex k) the face across the undirected edge; -1 boundary, -2 shared by
+// more than two faces.
+void build_adjacency(const int *faces, int F, int V, int *adj) {
+    std::vector<std::pair<long long, int>> e;
+    e.reserve(3 * (size_t)F);
+    for (int f = 0; f < F; ++f)
+        for (int k = 0; k < 3; ++k) {
+            const long long a = faces[3 * f + (k + 1) % 3], b = faces[3 * f + (k + 2) % 3];
+            e.push_back({std::min(a, b) * (long long)V + std::max(a, b), 3 * f + k});
+        }
+    std::sort(e.begin(), e.end());
+    size_t i = 0;
+    while (i < e.size()) {
+        size_t j = i;
+        while (j < e.size() && e[j].first == e[i].first) ++j;
+        const size_t n = j - i;
+        for (size_t q = i; q < j; ++q) {
+            int v = -1;
+            if (n == 2) v = e[q == i ? i + 1 : i].second / 3;
+            else if (n > 2) v = -2;
+            adj[e[q].second] = v;
+        }
+        i = j;
+    }
+}
+
+bool layout_ok(long long x) { return x >= 0 && x < (1LL << 31); }
+
+}  // namespace
+
+extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size, int32_t bin_capacity_scale,
+                                      dsm_plan **out_plan) {
+    if (!d || !out_plan) return DSM_ERR_INVALID_ARG;
+    *out_plan = nullptr;
+    if (tile_size == 0) tile_size = 16;
+    if (tile_size != 8 && tile_size != 16 && tile_size != 32) return DSM_ERR_INVALID_ARG;
+    if (bin_capacity_scale == 0) bin_capacity_scale = 32;
+    if (bin_capacity_scale < 0 || bin_capacity_scale > 1024) return DSM_ERR_INVALID_ARG;
+    const int B = d->num_scenes, L = d->num_lights, Cm = d->num_cameras, R = d->num_renders;
+    if (B < 1 || L < 0 || Cm < 0 || R < 0 || !d->vert_offsets || !d->face_offsets) return DSM_ERR_INVALID_ARG;
+    if ((L > 0 && !d->lights) || (Cm > 0 && !d->cameras) || (R > 0 && (!d->renders || !d->render_light_list)))
+        return DSM_ERR_INVALID_ARG;
+    if (d->channels != 1 && d->channels != 3) return DSM_ERR_INVALID_ARG;
+    if (d->vert_offsets[0] != 0 || d->face_offsets[0] != 0) return DSM_ERR_INVALID_ARG;
+    for (int b = 0; b < B; ++b)
+        if (d->vert_offsets[b + 1] < d->vert_offsets[b] || d->face_offsets[b + 1] < d->face_offsets[b])
+            return DSM_ERR_INVALID_ARG;
+    const long long Vt = d->vert_offsets[B], Ft = d->face_offsets[B];
+    if (!layout_ok(3 * Vt) || !layout_ok(3 * Ft) || (Ft > 0 && !d->faces)) return DSM_ERR_INVALID_ARG;
+    for (int b = 0; b < B; ++b) {
+        const int nv = d->vert_offsets[b + 1] - d->vert_offsets[b];
+        for (long long f = d->face_offsets[b]; f < d->face_offsets[b + 1]; ++f)
+            for (int k = 0; k < 3; ++k)
+                if (d->faces[3 * f + k] < 0 || d->faces[3 * f + k] >= nv) return DSM_ERR_INVALID_ARG;
+        if (d->pose_counts && (d->pose_counts[b] < 0 || d->pose_counts[b] > nv)) return DSM_ERR_INVALID_ARG;
+    }
+    for (int l = 0; l < L; ++l) {
+        const dsm_light_desc &x = d->lights[l];
+        if (x.type < 0 || x.type > 2 || x.scene < 0 || x.scene >= B) return DSM_ERR_INVALID_ARG;
+        if (!valid_filter(x.resolution, x.filter, x.k)) return DSM_ERR_INVALID_ARG;
+        if (!(x.znear > 0 && x.zfar > x.znear) || !std::isfinite(x.zfar)) return DSM_ERR_INVALID_ARG;
+        if (x.type == DSM_LIGHT_DIRECTIONAL && !(x.ortho_half > 0 && x.dir_distance > 0)) return DSM_ERR_INVALID_ARG;
+        if (x.type != DSM_LIGHT_DIRECTIONAL && !(x.fov_deg > 0 && x.fov_deg < 180)) return DSM_ERR_INVALID_ARG;
+        if (!finite3(x.target) || !finite3(x.up) || !(x.min_variance >= 0) || !std::isfinite(x.intensity))
+            return DSM_ERR_INVALID_ARG;
+    }
+    for (int c = 0; c < Cm; ++c) {
+        const dsm_camera_desc &x = d->cameras[c];
+        if (x.width < 1 || x.height < 1 || x.width > DSM_MAX_RESOLUTION || x.height > DSM_MAX_RESOLUTION)
+            return DSM_ERR_INVALID_ARG;
+        if (x.scene < 0 || x.scene >= B || !(x.fov_deg > 0 && x.fov_deg < 180) || !(x.znear > 0 && x.zfar > x.znear))
+            return DSM_ERR_INVALID_ARG;
+        if (!finite3(x.eye) || !finite3(x.target) || !finite3(x.up)) return DSM_ERR_INVALID_ARG;
+    }
+    long long list_len = 0;
+    for (int r = 0; r < R; ++r) {
+        const dsm_render_desc &x = d->renders[r];
+        if (x.camera < 0 || x.camera >= Cm || x.light_begin < 0 || x.light_count < 0 ||
+            x.light_count > DSM_MAX_LIGHTS_PER_RENDER)
+            return DSM_ERR_INVALID_ARG;
+        list_len = std::max<long long>(list_len, (long long)x.light_begin + x.light_count);
+        for (int q = 0; q < x.light_count; ++q) {
+            const int l = d->render_light_list[x.light_begin + q];
+            if (l < 0 || l >= L || d->lights[l].scene != d->cameras[x.camera].scene) return DSM_ERR_INVALID_ARG;
+        }
+    }
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return DSM_ERR_NO_DEVICE;
+    dsm_plan *p = new (std::nothrow) dsm_plan();
+    if (!p) return DSM_ERR_OUT_OF_MEMORY;
+    p->B = B; p->L = L; p->Cm = Cm; p->R = R; p->C = d->channels; p->nviews = L + Cm;
+    p->camera_antialias = d->camera_antialias != 0;
+    p->V_total = Vt; p->F_total = Ft;
+    p->tile = tile_size;
+    p->bin_scale = bin_capacity_scale;
+    p->vert_off.assign(d->vert_offsets, d->vert_offsets + B + 1);
+    p->face_off.assign(d->face_offsets, d->face_offsets + B + 1);
+    p->pose_counts.assign(B, 0);
+    p->pose_centers.assign(3 * (size_t)B, 0.f);
+    if (d->pose_counts) p->pose_counts.assign(d->pose_counts, d->pose_counts + B);
+    if (d->pose_centers) p->pose_centers.assign(d->pose_centers, d->pose_centers + 3 * (size_t)B);
+    for (int b = 0; b < B; ++b) p->max_pose_verts = std::max(p->max_pose_verts, p->pose_counts[b]);
+
+    // views: lights then cameras
+    long long clip = 0, tri = 0, pix = 0, maps = 0, tiles = 0;
+    auto add_view = [&](ViewConst &v, int scene, int W, int H) {
+        v.scene = scene;
+        v.W = W;
+        v.H = H;
+        v.vert_off = p->vert_off[scene];
+        v.nverts = p->vert_off[scene + 1] - p->vert_off[scene];
+        v.face_off = p->face_off[scene];
+        v.nfaces = p->face_off[scene + 1] - p->face_off[scene];
+        v.clip_off = (int)clip;
+        v.setup_off = (int)tri;
+        v.pix_off = pix;
+        v.tile_off = (int)tiles;
+        v.tiles_x = (W + tile_size - 1) / tile_size;
+        v.tiles_y = (H + tile_size - 1) / tile_size;
+        clip += v.nverts;
+        tri += v.nfaces;
+        pix += (long long)W * H;
+        tiles += (long long)v.tiles_x * v.tiles_y;
+        p->max_verts = std::max(p->max_verts, v.nverts);
+        p->max_faces = std::max(p->max_faces, v.nfaces);
+    };
+    p->views_h.resize(p->nviews);
+    p->light_cams_h.resize(L);
+    for (int l = 0; l < L; ++l) {
+        const dsm_light_desc &x = d->lights[l];
+        ViewConst v;
+        memset(&v, 0, sizeof(v));
+        v.kind = x.type == DSM_LIGHT_DIRECTIONAL ? kDirectional : (x.type == DSM_LIGHT_POINT ? kPoint : kSpot);
+        v.zfar = x.zfar;
+        v.cos_half = (float)cos((double)x.fov_deg * (M_PI / 180.0) / 2.0);
+        v.intensity = x.intensity;
+        v.min_var = x.min_variance;
+        v.antialias = x.antialias != 0;
+        add_view(v, x.scene, x.resolution, x.resolution);
+        v.map_off = maps;
+        maps += 2LL * x.resolution * x.resolution;
+        p->max_light_texels = std::max(p->max_light_texels, x.resolution * x.resolution);
+        p->views_h[l] = v;
+        CamStatic &cs = p->light_cams_h[l];
+        memset(&cs, 0, sizeof(cs));
+        cs.kind = v.kind;
+        for (int i = 0; i < 3; ++i) { cs.target[i] = x.target[i]; cs.up[i] = x.up[i]; }
+        cs.focal = 1.0 / tan((double)x.fov_deg * (M_PI / 180.0) / 2.0);
+        cs.aspect = 1.0;
+        cs.znear = x.znear;
+        cs.zfar = x.zfar;
+        cs.dir_distance = x.dir_distance;
+        cs.ortho_half = x.ortho_half;
+        p->blur_rmax = std::max(p->blur_rmax, (x.k - 1) / 2);
+    }
+    for (int c = 0; c < Cm; ++c) {
+        const dsm_camera_desc &x = d->cameras[c];
+        ViewConst v;
+        memset(&v, 0, sizeof(v));
+        v.kind = kCamera;
+        v.zfar = x.zfar;
+        v.antialias = p->camera_antialias;
+        add_view(v, x.scene, x.width, x.height);
+        CamStatic cs;
+        memset(&cs, 0, sizeof(cs));
+        cs.kind = kCamera;
+        for (int i = 0; i < 3; ++i) cs.up[i] = x.up[i];
+        cs.focal = 1.0 / tan((double)x.fov_deg * (M_PI / 180.0) / 2.0);
+        cs.aspect = (double)x.width / (double)x.height;
+        cs.znear = x.znear;
+        cs.zfar = x.zfar;
+        const Vec3<double> eye{x.eye[0], x.eye[1], x.eye[2]}, tg{x.target[0], x.target[1], x.target[2]};
+        double M[16];
+        view_projection<double>(cs, eye, tg, M);
+        for (int i = 0; i < 16; ++i) v.M[i] = (float)M[i];
+        p->max_cam_pix = std::max(p->max_cam_pix, x.width * x.height);
+        p->views_h[L + c] = v;
+    }
+    long long img = 0;
+    p->renders_h.resize(R);
+    for (int r = 0; r < R; ++r) {
+        const dsm_render_desc &x = d->renders[r];
+        RenderConst rc;
+        memset(&rc, 0, sizeof(rc));
+        rc.camera_view = L + x.camera;
+        rc.light_begin = x.light_begin;
+        rc.light_count = x.light_count;
+        rc.W = d->cameras[x.camera].width;
+        rc.H = d->cameras[x.camera].height;
+        rc.img_off = img;
+        rc.pix_off = p->views_h[L + x.camera].pix_off;
+        img += (long long)rc.W * rc.H * p->C;
+        p->renders_h[r] = rc;
+    }
+    p->render_lights_h.assign(d->render_light_list, d->render_light_list + list_len);
+    p->nclip = (int)clip;
+    p->ntri = (int)tri;
+    p->ntiles = (int)tiles;
+    p->key_count = pix;
+    p->map_floats = maps;
+    p->image_floats = img;
+    if (!layout_ok(clip) || !layout_ok(tri) || !layout_ok(tiles) || !layout_ok(pix) || !layout_ok(maps) ||
+        !layout_ok(img) || !layout_ok((long long)bin_capacity_scale * (tri + tiles) / 4)) {
+        delete p;
+        return DSM_ERR_INVALID_ARG;
+    }
+    p->capacity = (unsigned)((long long)bin_capacity_scale * (tri + tiles) / 4);
+
+    // blur jobs over all light maps, one flattened tile grid
+    int btiles = 0;
+    for (int l = 0; l < L; ++l) {
+        const dsm_light_desc &x = d->lights[l];
+        BlurJob j;
+        memset(&j, 0, sizeof(j));
+        j.S = x.resolution;
+        j.k = x.k;
+        j.in_off = p->views_h[l].map_off;
+        j.out_off = p->views_h[l].map_off;
+        j.tile_off = btiles;
+        j.tiles_x = blur_tiles_x(x.resolution);
+        filter_taps_host(x.filter, x.k, x.sigma, j.w);
+        btiles += blur_tiles(x.resolution, p->blur_rmax);
+        p->blur_jobs_h.push_back(j);
+    }
+    p->blur_tiles = btiles;
+
+    // saved layout
+    size_t o = 0;
+    p->sv_keys = o; o = align_up(o + 8 * (size_t)pix);
+    p->sv_clip = o; o = align_up(o + 16 * (size_t)clip);
+    p->sv_setup = o; o = align_up(o + sizeof(TriSetup) * (size_t)tri);
+    p->sv_F0 = o; o = align_up(o + 4 * (size_t)maps);
+    p->sv_M = o; o = align_up(o + 4 * (size_t)maps);
+    p->sv_img0 = o; o = align_up(o + 4 * (size_t)img);
+    p->saved_bytes = std::max<size_t>(o, kAlign);
+    // scratch layout
+    o = 0;
+    p->sc_counters = o; o = align_up(o + sizeof(DevCounters));
+    p->sc_tile_cnt = o; o = align_up(o + 4 * ((size_t)tiles + 1));
+    p->sc_tile_cursor = o; o = align_up(o + 4 * ((size_t)tiles + 1));
+    p->sc_zero_fwd_end = o;
+    p->sc_pair_cnt = o; o = align_up(o + 4 * ((size_t)tri + 1));
+    p->sc_pair_off = o; o = align_up(o + 4 * ((size_t)tri + 1));
+    p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
+    p->sc_tile_start = o; o = align_up(o + 4 * ((size_t)tiles + 1));
+    p->sc_bins = o; o = align_up(o + 4 * (size_t)p->capacity);
+    p->sc_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
+    p->sc_F1 = o; o = align_up(o + 4 * (size_t)maps);
+    p->sc_gimg0 = o; o = align_up(o + 4 * (size_t)img);
+    p->sc_gM = o; o = align_up(o + 4 * (size_t)maps);
+    p->sc_gclip = o; o = align_up(o + 16 * (size_t)clip);
+    p->sc_glight = o; o = align_up(o + 4 * 24 * (size_t)std::max(L, 1));
+    p->sc_galbedo = o; o = align_up(o + 4 * (size_t)Ft * p->C);
+    p->sc_gF1 = o; o = align_up(o + 4 * (size_t)maps);
+    p->scratch_bytes = o;
+
+    // device uploads
+    std::vector<int> adj(3 * (size_t)Ft, -1);
+    for (int b = 0; b < B; ++b)
+        build_adjacency(d->faces + 3 * (size_t)p->face_off[b], p->face_off[b + 1] - p->face_off[b],
+                        p->vert_off[b + 1] - p->vert_off[b], adj.data() + 3 * (size_t)p->face_off[b]);
+    std::vector<int> tile_view((size_t)tiles);
+    for (int v = 0; v < p->nviews; ++v) {
+        const ViewConst &x = p->views_h[v];
+        for (int t = 0; t < x.tiles_x * x.tiles_y; ++t) tile_view[x.tile_off + t] = v;
+    }
+    dsm_status st = DSM_OK;
+    if (st == DSM_OK) st = upload(&p->views_d, p->views_h.data(), p->views_h.size());
+    if (st == DSM_OK) st = upload(&p->light_cams_d, p->light_cams_h.data(), p->light_cams_h.size());
+    if (st == DSM_OK) st = upload(&p->renders_d, p->renders_h.data(), p->renders_h.size());
+    if (st == DSM_OK) st = upload(&p->render_lights_d, p->render_lights_h.data(), p->render_lights_h.size());
+    if (st == DSM_OK) st = upload(&p->faces_d, d->faces, 3 * (size_t)Ft);
+    if (st == DSM_OK) st = upload(&p->adj_d, adj.data(), adj.size());
+    if (st == DSM_OK) st = upload(&p->tile_view_d, tile_view.data(), tile_view.size());
+    if (st == DSM_OK) st = upload(&p->blur_jobs_d, p->blur_jobs_h.data(), p->blur_jobs_h.size());
+    if (st == DSM_OK) st = upload(&p->scene_vert_off_d, p->vert_off.data(), p->vert_off.size());
+    if (st == DSM_OK) st = upload(&p->pose_counts_d, p->pose_counts.data(), p->pose_counts.size());
+    if (st == DSM_OK) st = upload(&p->pose_centers_d, p->pose_centers.data(), p->pose_centers.size());
+    if (st != DSM_OK) {
+        dsm_plan_destroy(p);
+        return st;
+    }
+    *out_plan = p;
+    return DSM_OK;
+}
+
+extern "C" void dsm_plan_destroy(dsm_plan *p) {
+    if (!p) return;
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    void *bufs[] = {p->views_d, p->light_cams_d, p->renders_d, p->render_lights_d, p->faces_d, p->adj_d,
+                    p->tile_view_d, p->blur_jobs_d, p->scene_vert_off_d, p->pose_counts_d, p->pose_centers_d};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+extern "C" dsm_status dsm_plan_info_get(const dsm_plan *p, dsm_plan_info *out) {
+    if (!p || !out) return DSM_ERR_INVALID_ARG;
+    out->total_vertices = p->V_total;
+    out->total_faces = p->F_total;
+    out->image_floats = p->image_floats;
+    out->saved_bytes = (int64_t)p->saved_bytes;
+    out->scratch_bytes = (int64_t)p->scratch_bytes;
+    out->map_floats = p->map_floats;
+    out->tile_size = p->tile;
+    out->bin_capacity_scale = p->bin_scale;
+    return DSM_OK;
+}
+
+#define DSM_TRY(x)                                   \
+    do {                                             \
+        if ((x) != hipSuccess) return DSM_ERR_HIP;   \
+    } while (0)
+
+namespace {
+
+template <class T>
+T *at(void *base, size_t off) { return (T *)((char *)base + off); }
+template <class T>
+const T *at(const void *base, size_t off) { return (const T *)((const char *)base + off); }
+
+dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo, void *saved,
+                           void *scratch, float *images, hipStream_t s) {
+    DevCounters *cnt = at<DevCounters>(scratch, p->sc_counters);
+    unsigned *tile_cnt = at<unsigned>(scratch, p->sc_tile_cnt);
+    unsigned *tile_cursor = at<unsigned>(scratch, p->sc_tile_cursor);
+    unsigned *pair_cnt = at<unsigned>(scratch, p->sc_pair_cnt);
+    unsigned *pair_off = at<unsigned>(scratch, p->sc_pair_off);
+    unsigned *scan = at<unsigned>(scratch, p->sc_scan);
+    unsigned *tile_start = at<unsigned>(scratch, p->sc_tile_start);
+    unsigned *bins = at<unsigned>(scratch, p->sc_bins);
+    unsigned *overflow = at<unsigned>(scratch, p->sc_overflow);
+    float *F1 = at<float>(scratch, p->sc_F1);
+    unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
+    float4 *clip = at<float4>(saved, p->sv_clip);
+    TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
+    float *F0 = at<float>(saved, p->sv_F0);
+    float *Mm = at<float>(saved, p->sv_M);
+    float *img0 = at<float>(saved, p->sv_img0);
+
+    DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
+    DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
+    DSM_TRY(launch_setup(p->views_d, p->nviews, p->max_faces, p->faces_d, clip, setup, pair_cnt, p->tile, cnt, s));
+    DSM_TRY(launch_scan(pair_cnt, pair_off, scan, p->ntri, s));
+    DSM_TRY(launch_binning(p->views_d, setup, pair_off, p->ntri, p->capacity, p->tile, tile_cnt, tile_start,
+                           tile_cursor, scan, p->ntiles, bins, overflow, cnt, s));
+    DSM_TRY(launch_raster(p->views_d, p->tile_view_d, p->ntiles, p->tile, setup, tile_start, bins, overflow, cnt, cnt,
+                          keys, s));
+    DSM_TRY(launch_resolve(p->views_d, p->L, p->max_light_texels, p->faces_d, verts, clip, keys, F0, s));
+    DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, p->adj_d,
+                              verts, keys, F0, F1, 2, s));
+    DSM_TRY(launch_blur(p->blur_jobs_d, p->L, p->blur_tiles, F1, Mm, false, p->blur_rmax, s));
+    DSM_TRY(launch_lookup(p->views_d, p->renders_d, p->R, p->max_cam_pix, p->render_lights_d, p->faces_d, verts,
+                          albedo, clip, keys, Mm, img0, p->C, s));
+    DSM_TRY(launch_aa_forward(false, p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, p->adj_d,
+                              verts, keys, img0, images, p->C, s));
+    return DSM_OK;
+}
+
+dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
+                            const void *saved, void *scratch, const float *gimg, float *gverts, float *glparams,
+                            float *galbedo, hipStream_t s) {
+    const unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
+    const float4 *clip = at<float4>(saved, p->sv_clip);
+    const TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
+    const float *F0 = at<float>(saved, p->sv_F0);
+    const float *Mm = at<float>(saved, p->sv_M);
+    const float *img0 = at<float>(saved, p->sv_img0);
+    float *gimg0 = at<float>(scratch, p->sc_gimg0);
+    float *gM = at<float>(scratch, p->sc_gM);
+    float4 *gclip = at<float4>(scratch, p->sc_gclip);
+    float *glight = at<float>(scratch, p->sc_glight);
+    float *galb = galbedo ? galbedo : at<float>(scratch, p->sc_galbedo);
+    float *gF1 = at<float>(scratch, p->sc_gF1);
+
+    DSM_TRY(zero_async(gM, p->sc_gF1 - p->sc_gM, s));   // gM, gclip, glight, scratch galbedo
+    DSM_TRY(zero_async(gverts, 12 * (size_t)p->V_total, s));
+    if (galbedo) DSM_TRY(zero_async(galbedo, 4 * (size_t)p->F_total * p->C, s));
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
+    DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, p->adj_d,
+                                      verts, keys, img0, gimg, gimg0, gclip, p->C, s));
+    DSM_TRY(launch_lookup_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, p->render_lights_d, p->faces_d,
+                                   verts, albedo, clip, keys, Mm, gimg0, gM, gverts, gclip, glight, galb, p->C, s));
+    DSM_TRY(launch_blur(p->blur_jobs_d, p->L, p->blur_tiles, gM, gF1, true, p->blur_rmax, s));
+    DSM_TRY(launch_light_backward(p->views_d, p->L, p->max_light_texels, setup, p->faces_d, p->adj_d, verts, clip,
+                                  keys, F0, gF1, gverts, gclip, glight, s));
+    DSM_TRY(launch_transform_backward(p->views_d, p->nviews, p->L, p->max_verts, verts, gclip, gverts, glight, s));
+    DSM_TRY(launch_light_param_grad(p->light_cams_d, lparams, glight, glparams, p->L, s));
+    return DSM_OK;
+}
+
+bool buffers_ok(const dsm_plan *p, const void *saved, size_t saved_bytes, const void *scratch, size_t scratch_bytes,
+                dsm_status *st) {
+    if (!saved || !scratch) { *st = DSM_ERR_INVALID_ARG; return false; }
+    if (saved_bytes < p->saved_bytes || scratch_bytes < p->scratch_bytes) { *st = DSM_ERR_WORKSPACE_TOO_SMALL; return false; }
+    if (((uintptr_t)saved & 255) || ((uintptr_t)scratch & 255)) { *st = DSM_ERR_INVALID_ARG; return false; }
+    return true;
+}
+
+}  // namespace
+
+extern "C" dsm_status dsm_forward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
+                                  void *saved, size_t saved_bytes, void *scratch, size_t scratch_bytes,
+                                  float *images, dsm_stream stream) {
+    if (!p) return DSM_ERR_INVALID_ARG;
+    dsm_status st;
+    if (!buffers_ok(p, saved, saved_bytes, scratch, scratch_bytes, &st)) return st;
+    if ((p->V_total > 0 && !verts) || (p->L > 0 && !lparams) || (p->F_total > 0 && !albedo) ||
+        (p->image_floats > 0 && !images))
+        return DSM_ERR_INVALID_ARG;
+    return enqueue_forward(p, verts, lparams, albedo, saved, scratch, images, (hipStream_t)stream);
+}
+
+extern "C" dsm_status dsm_backward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
+                                   const void *saved, size_t saved_bytes, void *scratch, size_t scratch_bytes,
+                                   const float *gimg, float *gverts, float *glparams, float *galbedo,
+                                   dsm_stream stream) {
+    if (!p) return DSM_ERR_INVALID_ARG;
+    dsm_status st;
+    if (!buffers_ok(p, saved, saved_bytes, scratch, scratch_bytes, &st)) return st;
+    if ((p->V_total > 0 && (!verts || !gverts)) || (p->L > 0 && (!lparams || !glparams)) ||
+        (p->F_total > 0 && !albedo) || (p->image_floats > 0 && !gimg))
+        return DSM_ERR_INVALID_ARG;
+    return enqueue_backward(p, verts, lparams, albedo, saved, scratch, gimg, gverts, glparams, galbedo,
+                            (hipStream_t)stream);
+}
+
+extern "C" dsm_status dsm_pose_forward(dsm_plan *p, const float *local, const float *poses, float *world,
+                                       dsm_stream stream) {
+    if (!p || (p->V_total > 0 && (!local || !world)) || !poses) return DSM_ERR_INVALID_ARG;
+    if (local == world) return DSM_ERR_INVALID_ARG;
+    DSM_TRY(launch_pose(p->scene_vert_off_d, p->pose_counts_d, p->pose_centers_d, p->B,
+                        std::max(p->max_verts, 1), local, poses, world, (hipStream_t)stream));
+    return DSM_OK;
+}
+
+extern "C" dsm_status dsm_pose_backward(dsm_plan *p, const float *local, const float *poses, const float *gworld,
+                                        float *gposes, dsm_stream stream) {
+    if (!p || (p->V_total > 0 && (!local || !gworld)) || !poses || !gposes) return DSM_ERR_INVALID_ARG;
+    DSM_TRY(zero_async(gposes, 4 * 6 * (size_t)p->B, (hipStream_t)stream));
+    DSM_TRY(launch_pose_backward(p->scene_vert_off_d, p->pose_counts_d, p->B, std::max(p->max_pose_verts, 1), local,
+                                 poses, gworld, gposes, (hipStream_t)stream));
+    return DSM_OK;
+}
+
+extern "C" dsm_status dsm_graph_capture(dsm_plan *p, const float *local, const float *poses, float *verts,
+                                        const float *lparams, const float *albedo, void *saved, size_t saved_bytes,
+                                        void *scratch, size_t scratch_bytes, float *images, const float *gimg,
+                                        float *gverts, float *glparams, float *galbedo, float *gposes,
+                                        dsm_stream stream) {
+    if (!p || !stream) return DSM_ERR_INVALID_ARG;
+    dsm_status st;
+    if (!buffers_ok(p, saved, saved_bytes, scratch, scratch_bytes, &st)) return st;
+    if (!verts || !lparams || !albedo || !images || !gimg || !gverts || !glparams) return DSM_ERR_INVALID_ARG;
+    if (poses && (!local || !gposes)) return DSM_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    DSM_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    dsm_status r = DSM_OK;
+    if (poses) r = dsm_pose_forward(p, local, poses, verts, stream);
+    if (r == DSM_OK) r = enqueue_forward(p, verts, lparams, albedo, saved, scratch, images, s);
+    if (r == DSM_OK)
+        r = enqueue_backward(p, verts, lparams, albedo, saved, scratch, gimg, gverts, glparams, galbedo, s);
+    if (r == DSM_OK && poses) r = dsm_pose_backward(p, local, poses, gverts, gposes, stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (r != DSM_OK) { if (g) (void)hipGraphDestroy(g); return r; }
+    if (e != hipSuccess || !g) return DSM_ERR_HIP;
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) { (void)hipGraphDestroy(g); return DSM_ERR_HIP; }
+    p->graph = g;
+    p->graph_exec = x;
+    return DSM_OK;
+}
+
+extern "C" dsm_status dsm_graph_launch(dsm_plan *p, dsm_stream stream) {
+    if (!p || !p->graph_exec) return DSM_ERR_INVALID_ARG;
+    DSM_TRY(hipGraphLaunch(p->graph_exec, (hipStream_t)stream));
+    return DSM_OK;
+}
+
+extern "C" dsm_status dsm_get_view_keys(const dsm_plan *p, const void *saved, int32_t view, uint64_t *out,
+                                        dsm_stream stream) {
+    if (!p || !saved || !out || view < 0 || view >= p->nviews) return DSM_ERR_INVALID_ARG;
+    const ViewConst &v = p->views_h[view];
+    DSM_TRY(hipMemcpyAsync(out, at<char>(saved, p->sv_keys + 8 * (size_t)v.pix_off), 8 * (size_t)v.W * v.H,
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return DSM_OK;
+}
+
+extern "C" dsm_status dsm_get_light_maps(const dsm_plan *p, const void *saved, const void *scratch, int32_t light,
+                                         int32_t which, float *out, dsm_stream stream) {
+    if (!p || !out || light < 0 || light >= p->L || which < 0 || which > 2) return DSM_ERR_INVALID_ARG;
+    if ((which != 1 && !saved) || (which == 1 && !scratch)) return DSM_ERR_INVALID_ARG;
+    const ViewConst &v = p->views_h[light];
+    const size_t base = which == 0 ? p->sv_F0 : which == 1 ? p->sc_F1 : p->sv_M;
+    const void *src = which == 1 ? scratch : saved;
+    DSM_TRY(hipMemcpyAsync(out, at<char>(src, base + 4 * (size_t)v.map_off), 8 * (size_t)v.W * v.W,
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return DSM_OK;
+}
+
+extern "C" dsm_status dsm_get_render_image0(const dsm_plan *p, const void *saved, int32_t render, float *out,
+                                            dsm_stream stream) {
+    if (!p || !saved || !out || render < 0 || render >= p->R) return DSM_ERR_INVALID_ARG;
+    const RenderConst &r = p->renders_h[render];
+    DSM_TRY(hipMemcpyAsync(out, at<char>(saved, p->sv_img0 + 4 * (size_t)r.img_off),
+                           4 * (size_t)r.W * r.H * p->C, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return DSM_OK;
+}
+
+extern "C" dsm_status dsm_get_stats(const dsm_plan *p, const void *scratch, dsm_stats *out, dsm_stream stream) {
+    if (!p || !scratch || !out) return DSM_ERR_INVALID_ARG;
+    DevCounters c;
+    DSM_TRY(hipMemcpyAsync(&c, at<char>(scratch, p->sc_counters), sizeof(c), hipMemcpyDeviceToHost,
+                           (hipStream_t)stream));
+    DSM_TRY(hipStreamSynchronize((hipStream_t)stream));
+    out->culled_triangles = c.culled;
+    out->binned_pairs = c.pairs;
+    out->overflow_triangles = c.overflow;
+    out->bad_indices = c.bad_indices;
+    return DSM_OK;
+}

@@ -1,0 +1,161 @@
+// Internal layout shared by the HIP translation units of the library.
+// Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dsm.h"
+
+namespace dsm {
+
+constexpr int kSub = 256;              // 8 sub-pixel bits of the fixed-point grid
+constexpr float kGuard = 32768.0f;     // |screen coordinate| limit in pixels
+constexpr uint64_t kBgKey = ~0ull;     // background key (no triangle)
+constexpr int kMaxTaps = 32;
+
+enum ViewKind { kDirectional = 0, kPoint = 1, kSpot = 2, kCamera = 3 };
+
+// One view: a light camera (views [0, L)) or a viewer camera (views [L, L+Cm)).
+// Light views get M / pos / dir rewritten on the device by every forward.
+struct ViewConst {
+    float M[16];        // row-major view-projection, clip = M [x, 1]
+    float pos[3];       // point/spot: position; directional: eye
+    float dir[3];       // directional: unit travel direction; spot: cone axis
+    float zfar;         // distance normalization
+    float cos_half;     // spot cone
+    float intensity;
+    float min_var;
+    int kind;
+    int scene;
+    int W, H;
+    int vert_off, nverts;
+    int face_off, nfaces;
+    int clip_off;       // first vertex of this view in the clip / gclip arrays
+    int setup_off;      // first triangle of this view in the per-(view, triangle) arrays
+    long long pix_off;  // first sample of this view in the key array
+    int tile_off;       // first tile of this view in the global tile list
+    int tiles_x, tiles_y;
+    int antialias;
+    long long map_off;  // light views: first texel of the 2-channel maps (plane stride S*S)
+    int pad[2];
+};
+
+struct RenderConst {
+    int camera_view;    // view index of the camera
+    int light_begin;    // range into the device list of light view indices
+    int light_count;
+    int W, H;
+    int pad;
+    long long img_off;  // first float of the [H,W,C] image
+    long long pix_off;  // camera view's first sample (keys)
+};
+
+// Per (view, triangle) fixed-point setup, written by the setup kernel.
+struct TriSetup {
+    long long A;                 // doubled area, > 0 when valid
+    int X[3], Y[3];              // oriented fixed-point screen coordinates
+    float z[3];                  // oriented z01
+    unsigned short bx0, by0, bx1, by1;  // inclusive pixel bbox, clipped to the view
+    signed char facing;          // +1 / -1 orientation before re-orienting, 0 if not rasterized
+    unsigned char swapped;       // 2nd and 3rd vertex exchanged
+    unsigned char pad0, pad1;
+    int pad2[2];
+};
+static_assert(sizeof(TriSetup) == 64, "TriSetup must stay 64 bytes");
+
+struct BlurJob {
+    int S;
+    int k;
+    long long in_off;            // first float of the 2-channel input map
+    long long out_off;
+    int tile_off;                // first tile of this job
+    int tiles_x;
+    float w[kMaxTaps];
+};
+
+// Counters written by the device, read by dsm_get_stats.
+struct DevCounters {
+    unsigned long long culled;
+    unsigned long long pairs;
+    unsigned long long overflow;
+    unsigned long long bad_indices;
+    unsigned int overflow_list_len;
+    unsigned int pad[7];
+};
+
+// ----------------------------------------------------------------------------- helpers
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void atomic_add_f32(float *p, float v) {
+    if (v != 0.0f) atomicAdd(p, v);
+}
+
+}  // namespace dsm
+
+// Host-side launchers implemented per translation unit.
+namespace dsm {
+hipError_t launch_blur(const BlurJob *jobs_dev, int njobs, int total_tiles, const float *in, float *out,
+                       bool adjoint, int rmax, hipStream_t s);
+int blur_tile_height(int rmax);
+hipError_t launch_blur_uniform(const BlurJob &job, int n_maps, const float *in, float *out, bool adjoint,
+                               hipStream_t s);
+int blur_tiles(int S, int rmax);
+int blur_tiles_x(int S);
+bool valid_filter(int S, int filter, int k);
+
+struct CamStatic;
+hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, hipStream_t s);
+hipError_t launch_light_param_grad(const CamStatic *cams, const float *params, const float *glight, float *gparams,
+                                   int L, hipStream_t s);
+hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
+                            hipStream_t s);
+hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const int *faces, const float4 *clip,
+                        TriSetup *setup, unsigned *pair_count, int tile, DevCounters *counters, hipStream_t s);
+int scan_scratch_words(int n);
+hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int n, hipStream_t s);
+hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,
+                          unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
+                          unsigned *tile_cursor, unsigned *scan_scratch, int ntiles, unsigned *bins,
+                          unsigned *overflow_list, DevCounters *counters, hipStream_t s);
+hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntiles, int tile, const TriSetup *setup,
+                         const unsigned *tile_start, const unsigned *bins, const unsigned *overflow_list,
+                         const DevCounters *counters_ro, DevCounters *counters, unsigned long long *keys,
+                         hipStream_t s);
+hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const int *faces, const float *verts,
+                          const float4 *clip, const unsigned long long *keys, float *F0, hipStream_t s);
+hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
+                             const TriSetup *setup, const int *faces, const int *adj, const float *verts,
+                             const unsigned long long *keys, const float *src, float *dst, int C, hipStream_t s);
+hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
+                         const int *render_lights, const int *faces, const float *verts, const float *albedo,
+                         const float4 *clip, const unsigned long long *keys, const float *maps, float *img0, int C,
+                         hipStream_t s);
+// backward
+hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
+                                     const TriSetup *setup, const int *faces, const int *adj, const float *verts,
+                                     const unsigned long long *keys, const float *img0, const float *gimg,
+                                     float *gimg0, float4 *gclip, int C, hipStream_t s);
+hipError_t launch_lookup_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
+                                  const int *render_lights, const int *faces, const float *verts,
+                                  const float *albedo, const float4 *clip, const unsigned long long *keys,
+                                  const float *maps, const float *gimg0, float *gmaps, float *gverts,
+                                  float4 *gclip, float *glight, float *galbedo, int C, hipStream_t s);
+hipError_t launch_light_backward(const ViewConst *views, int L, int max_texels, const TriSetup *setup,
+                                 const int *faces, const int *adj, const float *verts, const float4 *clip,
+                                 const unsigned long long *keys, const float *F0, const float *gF1, float *gverts,
+                                 float4 *gclip, float *glight, hipStream_t s);
+hipError_t launch_transform_backward(const ViewConst *views, int nviews, int L, int max_verts, const float *verts,
+                                     const float4 *gclip, float *gverts, float *glight, hipStream_t s);
+hipError_t launch_pose(const int *scene_vert_off, const int *pose_counts, const float *pose_centers, int B,
+                       int max_verts, const float *local, const float *poses, float *world, hipStream_t s);
+hipError_t launch_pose_backward(const int *scene_vert_off, const int *pose_counts, int B, int max_verts,
+                                const float *local, const float *poses, const float *gworld, float *gposes,
+                                hipStream_t s);
+void filter_taps_host(int filter, int k, float sigma, float *w);
+}  // namespace dsm

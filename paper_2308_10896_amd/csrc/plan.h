@@ -1,0 +1,53 @@
+// The plan: host copy of a batch description, device-resident mesh-static
+// data, and the byte layout of the caller's saved / scratch buffers.
+#pragma once
+
+#include <vector>
+
+#include "dsm_internal.h"
+#include "frames.h"
+
+struct dsm_plan {
+    // batch shape
+    int B = 0, L = 0, Cm = 0, R = 0, C = 1, nviews = 0;
+    int camera_antialias = 1;
+    long long V_total = 0, F_total = 0;
+    int tile = 16;
+    int bin_scale = 8;
+    unsigned capacity = 0;
+    int ntri = 0, ntiles = 0, nclip = 0;
+    int max_verts = 0, max_faces = 0, max_light_texels = 0, max_cam_pix = 0;
+    long long key_count = 0, map_floats = 0, image_floats = 0;
+    int blur_tiles = 0, blur_rmax = 0, max_pose_verts = 0;
+
+    std::vector<dsm::ViewConst> views_h;
+    std::vector<dsm::CamStatic> light_cams_h;
+    std::vector<dsm::RenderConst> renders_h;
+    std::vector<int> render_lights_h;
+    std::vector<int> vert_off, face_off, pose_counts;
+    std::vector<float> pose_centers;
+    std::vector<dsm::BlurJob> blur_jobs_h;
+
+    // plan-owned device data
+    dsm::ViewConst *views_d = nullptr;
+    dsm::CamStatic *light_cams_d = nullptr;
+    dsm::RenderConst *renders_d = nullptr;
+    int *render_lights_d = nullptr;
+    int *faces_d = nullptr;
+    int *adj_d = nullptr;
+    int *tile_view_d = nullptr;
+    dsm::BlurJob *blur_jobs_d = nullptr;
+    int *scene_vert_off_d = nullptr;    // [B+1]
+    int *pose_counts_d = nullptr;       // [B]
+    float *pose_centers_d = nullptr;    // [B,3]
+
+    // layout of the caller's saved buffer (byte offsets)
+    size_t sv_keys = 0, sv_clip = 0, sv_setup = 0, sv_F0 = 0, sv_M = 0, sv_img0 = 0, saved_bytes = 0;
+    // layout of the caller's scratch buffer (byte offsets)
+    size_t sc_counters = 0, sc_pair_cnt = 0, sc_pair_off = 0, sc_scan = 0, sc_tile_cnt = 0, sc_tile_start = 0,
+           sc_tile_cursor = 0, sc_bins = 0, sc_overflow = 0, sc_F1 = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
+           sc_gclip = 0, sc_glight = 0, sc_galbedo = 0, sc_zero_fwd_end = 0, scratch_bytes = 0;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};

@@ -1,0 +1,500 @@
+// Rasterization of every view of a batch (light views into shadow maps, Eq. 1;
+// camera views for deferred shading): vertex transform, fixed-point triangle
+// setup, tile binning, and a tile rasterizer producing a 64-bit
+// depth|triangle-id visibility buffer (the nearest surface per sample, ties
+// to the lower triangle index).
+//
+// Coverage conventions (shared with no other code; stated here in full):
+//  * clip = M [x,1] per row as ((m0*x + m1*y) + m2*z) + m3 in float32 (the
+//    library is built without contraction, so no fused multiply-add);
+//  * sx = (x/w + 1) * (W/2), sy = (1 - y/w) * (H/2); X = rint(256 sx),
+//    Y = rint(256 sy); pixel (i,j) is sampled at (256 i + 128, 256 j + 128);
+//  * a triangle is culled when a vertex has w <= 0, z/w < -1, or a screen
+//    coordinate outside (-32768, 32768); it is re-oriented to positive doubled
+//    area A (2nd and 3rd vertex swapped when A < 0), A == 0 is skipped;
+//  * edge e is opposite vertex e, E_e = dx (py - ya) - dy (px - xa) for the
+//    directed edge a -> b; a sample on an edge belongs to the triangle only
+//    for top (dy == 0, dx > 0) or left (dy < 0) edges;
+//  * z01 = 0.5 z/w + 0.5 per vertex, interpolated (z0 + b1 (z1-z0)) + b2 (z2-z0)
+//    with b_e = f32(E_e) / f32(A); samples with z01 outside [0,1] are dropped;
+//  * key = bits(z01) << 32 | local triangle index, minimum wins.
+#include "dsm_internal.h"
+#include "frames.h"
+
+namespace dsm {
+
+// ----------------------------------------------------------------------------- light frames
+
+// One thread per light: the light camera from its float32 parameter, in
+// float64, rounded to float32 for the rest of the pipeline.
+__global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    const double p[3] = {params[3 * l], params[3 * l + 1], params[3 * l + 2]};
+    double M[16], pos[3], dir[3];
+    light_frame<double>(cams[l], p, M, pos, dir);
+    ViewConst &v = views[l];
+    for (int i = 0; i < 16; ++i) v.M[i] = (float)M[i];
+    for (int i = 0; i < 3; ++i) {
+        v.pos[i] = (float)pos[i];
+        v.dir[i] = (float)dir[i];
+    }
+}
+
+// Derivatives of a light frame pulled back to its parameter: glight[l] holds
+// the accumulated gradient w.r.t. (M[16], pos[3], dir[3]).
+__global__ void light_param_grad_kernel(const CamStatic *cams, const float *params, const float *glight,
+                                        float *gparams, int L) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    Dual3 p[3];
+    for (int i = 0; i < 3; ++i) {
+        p[i].v = params[3 * l + i];
+        for (int j = 0; j < 3; ++j) p[i].d[j] = (i == j) ? 1.0 : 0.0;
+    }
+    Dual3 M[16], pos[3], dir[3];
+    light_frame<Dual3>(cams[l], p, M, pos, dir);
+    const float *g = glight + 24 * l;
+    double out[3] = {0, 0, 0};
+    for (int j = 0; j < 3; ++j) {
+        double acc = 0;
+        for (int i = 0; i < 16; ++i) acc += (double)g[i] * M[i].d[j];
+        for (int i = 0; i < 3; ++i) acc += (double)g[16 + i] * pos[i].d[j] + (double)g[19 + i] * dir[i].d[j];
+        out[j] = acc;
+    }
+    for (int j = 0; j < 3; ++j) gparams[3 * l + j] = (float)out[j];
+}
+
+// ----------------------------------------------------------------------------- transform
+
+__global__ void transform_kernel(const ViewConst *__restrict__ views, const float *__restrict__ verts,
+                                 float4 *__restrict__ clip) {
+    const ViewConst &v = views[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= v.nverts) return;
+    const float *p = verts + 3 * (size_t)(v.vert_off + i);
+    const float x = p[0], y = p[1], z = p[2];
+    const float *M = v.M;
+    float4 c;
+    c.x = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+    c.y = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
+    c.z = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
+    c.w = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
+    clip[v.clip_off + i] = c;
+}
+
+// ----------------------------------------------------------------------------- setup
+
+__device__ __forceinline__ int floor_div256(int a) { return a >= 0 ? (a >> 8) : -((-a + 255) >> 8); }
+
+__global__ void setup_kernel(const ViewConst *__restrict__ views, const int *__restrict__ faces,
+                             const float4 *__restrict__ clip, TriSetup *__restrict__ setup,
+                             unsigned *__restrict__ pair_count, int tile, DevCounters *counters) {
+    const int view = blockIdx.y;
+    const ViewConst &v = views[view];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= v.nfaces) return;
+    const int *f = faces + 3 * (size_t)(v.face_off + t);
+    int idx[3] = {f[0], f[1], f[2]};
+    bool bad = false;
+    for (int k = 0; k < 3; ++k)
+        if (idx[k] < 0 || idx[k] >= v.nverts) { bad = true; idx[k] = 0; }
+    int X[3], Y[3];
+    float z[3];
+    bool ok = !bad;
+    const float hw = 0.5f * (float)v.W, hh = 0.5f * (float)v.H;
+    for (int k = 0; k < 3; ++k) {
+        const float4 c = clip[v.clip_off + idx[k]];
+        const float nx = c.x / c.w, ny = c.y / c.w, nz = c.z / c.w;
+        const float sx = (nx + 1.0f) * hw;
+        const float sy = (1.0f - ny) * hh;
+        const bool okv = (c.w > 0.0f) && (nz >= -1.0f) && (fabsf(sx) < kGuard) && (fabsf(sy) < kGuard);
+        ok = ok && okv;
+        X[k] = okv ? (int)rintf(sx * 256.0f) : 0;
+        Y[k] = okv ? (int)rintf(sy * 256.0f) : 0;
+        z[k] = 0.5f * nz + 0.5f;
+    }
+    long long A = (long long)(X[1] - X[0]) * (Y[2] - Y[0]) - (long long)(Y[1] - Y[0]) * (X[2] - X[0]);
+    const bool swapped = A < 0;
+    if (swapped) {
+        int ti = X[1]; X[1] = X[2]; X[2] = ti;
+        ti = Y[1]; Y[1] = Y[2]; Y[2] = ti;
+        float tz = z[1]; z[1] = z[2]; z[2] = tz;
+        A = -A;
+    }
+    const bool valid = ok && A > 0;
+    TriSetup s;
+    s.A = A;
+    for (int k = 0; k < 3; ++k) { s.X[k] = X[k]; s.Y[k] = Y[k]; s.z[k] = z[k]; }
+    s.facing = valid ? (swapped ? -1 : 1) : 0;
+    s.swapped = swapped ? 1 : 0;
+    s.pad0 = 0;
+    s.pad1 = 0;
+    s.pad2[0] = view;
+    s.pad2[1] = 0;
+    unsigned npairs = 0;
+    int i0 = 1, i1 = 0, j0 = 1, j1 = 0;
+    if (valid) {
+        const int mnx = min(X[0], min(X[1], X[2])), mxx = max(X[0], max(X[1], X[2]));
+        const int mny = min(Y[0], min(Y[1], Y[2])), mxy = max(Y[0], max(Y[1], Y[2]));
+        // pixel centres 256 i + 128 inside [mnx, mxx]
+        i0 = max(floor_div256(mnx - 128 + 255), 0);
+        i1 = min(floor_div256(mxx - 128), v.W - 1);
+        j0 = max(floor_div256(mny - 128 + 255), 0);
+        j1 = min(floor_div256(mxy - 128), v.H - 1);
+        if (i0 <= i1 && j0 <= j1) npairs = (unsigned)((i1 / tile - i0 / tile + 1) * (j1 / tile - j0 / tile + 1));
+    }
+    if (!(i0 <= i1 && j0 <= j1)) { i0 = 1; i1 = 0; j0 = 1; j1 = 0; }
+    s.bx0 = (unsigned short)i0;
+    s.bx1 = (unsigned short)i1;
+    s.by0 = (unsigned short)j0;
+    s.by1 = (unsigned short)j1;
+    setup[v.setup_off + t] = s;
+    pair_count[v.setup_off + t] = npairs;
+    const unsigned long long nc = __popcll(__ballot(!ok && !bad));
+    const unsigned long long nb = __popcll(__ballot(bad));
+    if ((threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(1)) - 1) {
+        if (nc) atomicAdd(&counters->culled, nc);
+        if (nb) atomicAdd(&counters->bad_indices, nb);
+    }
+}
+
+// ----------------------------------------------------------------------------- scan (exclusive, uint32)
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanBlock = kScanThreads * kScanPer;
+
+__device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned *total) {
+    __shared__ unsigned wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    unsigned base = 0, all = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        all += wsum[w];
+    }
+    __syncthreads();
+    *total = all;
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(const unsigned *in, unsigned *out,
+                                                                   unsigned *block_sums, int n) {
+    const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    unsigned vals[kScanPer];
+    unsigned sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        vals[k] = (base + k < n) ? in[base + k] : 0u;
+        sum += vals[k];
+    }
+    unsigned total;
+    unsigned off = block_exclusive_scan(sum, &total);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) out[base + k] = off;
+        off += vals[k];
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// single block; nb <= kScanBlock; writes the grand total to block_sums[nb]
+__global__ __launch_bounds__(kScanThreads) void scan_sums_kernel(unsigned *block_sums, int nb) {
+    const int base = threadIdx.x * kScanPer;
+    unsigned vals[kScanPer];
+    unsigned sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        vals[k] = (base + k < nb) ? block_sums[base + k] : 0u;
+        sum += vals[k];
+    }
+    unsigned total;
+    unsigned off = block_exclusive_scan(sum, &total);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < nb) block_sums[base + k] = off;
+        off += vals[k];
+    }
+    if (threadIdx.x == 0) block_sums[nb] = total;
+}
+
+__global__ void scan_add_kernel(unsigned *out, const unsigned *block_sums, int n, int nb) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += block_sums[i / kScanBlock];
+    if (i == 0) out[n] = block_sums[nb];
+}
+
+// Exclusive scan of n values in place-capable form: out[0..n] (out[n] = total).
+// scratch: at least scan_scratch_words(n) words.
+int scan_scratch_words(int n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int n, hipStream_t s) {
+    const int nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb > kScanBlock) return hipErrorInvalidValue;
+    if (nb > 0) hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, out, scratch, n);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, scratch, nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((n + 256) / 256), dim3(256), 0, s, out, scratch, n, nb);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- binning
+
+__device__ __forceinline__ int find_tri(const unsigned *pair_off, int ntri, unsigned p) {
+    // largest i in [0, ntri) with pair_off[i] <= p
+    int lo = 0, hi = ntri - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pair_off[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// FILL = false: count pairs per tile; FILL = true: scatter triangle indices.
+// Triangles whose pair range does not fit the bin capacity go to the
+// overflow path instead (decided per triangle, so never split).
+template <bool FILL>
+__global__ void bin_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
+                           const unsigned *__restrict__ pair_off, int ntri, unsigned capacity, int tile,
+                           unsigned *__restrict__ tile_count, const unsigned *__restrict__ tile_start,
+                           unsigned *__restrict__ bins) {
+    const unsigned total = min(pair_off[ntri], capacity);
+    for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+        const int i = find_tri(pair_off, ntri, p);
+        if (pair_off[i + 1] > capacity) continue;
+        const TriSetup &s = setup[i];
+        const ViewConst &v = views[s.pad2[0]];
+        const unsigned q = p - pair_off[i];
+        const int tx0 = s.bx0 / tile, tx1 = s.bx1 / tile, ty0 = s.by0 / tile;
+        const int ntx = tx1 - tx0 + 1;
+        const int tx = tx0 + (int)(q % ntx), ty = ty0 + (int)(q / ntx);
+        const int gt = v.tile_off + ty * v.tiles_x + tx;
+        if (!FILL) {
+            atomicAdd(&tile_count[gt], 1u);
+        } else {
+            const unsigned slot = atomicAdd(&tile_count[gt], 1u);
+            bins[tile_start[gt] + slot] = (unsigned)i;
+        }
+    }
+}
+
+__global__ void pairs_total_kernel(const unsigned *pair_off, int ntri, DevCounters *counters) {
+    counters->pairs = pair_off[ntri];
+}
+
+__global__ void overflow_list_kernel(const unsigned *__restrict__ pair_off, int ntri, unsigned capacity,
+                                     unsigned *__restrict__ list, DevCounters *counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntri) return;
+    const bool of = pair_off[i + 1] > pair_off[i] && pair_off[i + 1] > capacity;
+    if (of) {
+        const unsigned slot = atomicAdd(&counters->overflow_list_len, 1u);
+        list[slot] = (unsigned)i;
+    }
+}
+
+// ----------------------------------------------------------------------------- raster
+
+struct RasterTri {
+    int X[3], Y[3];
+    float z[3];
+    float fA;
+    unsigned short bx0, by0, bx1, by1;
+    unsigned tri;
+    int pad;
+};
+
+__device__ __forceinline__ RasterTri load_raster_tri(const TriSetup &s, unsigned local) {
+    RasterTri r;
+    for (int k = 0; k < 3; ++k) { r.X[k] = s.X[k]; r.Y[k] = s.Y[k]; r.z[k] = s.z[k]; }
+    r.fA = (float)(double)s.A;
+    r.bx0 = s.bx0; r.by0 = s.by0; r.bx1 = s.bx1; r.by1 = s.by1;
+    r.tri = local;
+    r.pad = 0;
+    return r;
+}
+
+__device__ __forceinline__ long long edge_fn(int xa, int ya, int xb, int yb, int px, int py) {
+    return (long long)(xb - xa) * (py - ya) - (long long)(yb - ya) * (px - xa);
+}
+
+__device__ __forceinline__ bool top_left(int xa, int ya, int xb, int yb) {
+    const int dx = xb - xa, dy = yb - ya;
+    return dy < 0 || (dy == 0 && dx > 0);
+}
+
+// Key of triangle r at pixel (i, j), or kBgKey when not covered.
+__device__ __forceinline__ unsigned long long sample_key(const RasterTri &r, int i, int j) {
+    if (i < r.bx0 || i > r.bx1 || j < r.by0 || j > r.by1) return kBgKey;
+    const int px = i * kSub + kSub / 2, py = j * kSub + kSub / 2;
+    const long long e0 = edge_fn(r.X[1], r.Y[1], r.X[2], r.Y[2], px, py);
+    const long long e1 = edge_fn(r.X[2], r.Y[2], r.X[0], r.Y[0], px, py);
+    const long long e2 = edge_fn(r.X[0], r.Y[0], r.X[1], r.Y[1], px, py);
+    const bool in0 = e0 > 0 || (e0 == 0 && top_left(r.X[1], r.Y[1], r.X[2], r.Y[2]));
+    const bool in1 = e1 > 0 || (e1 == 0 && top_left(r.X[2], r.Y[2], r.X[0], r.Y[0]));
+    const bool in2 = e2 > 0 || (e2 == 0 && top_left(r.X[0], r.Y[0], r.X[1], r.Y[1]));
+    if (!(in0 && in1 && in2)) return kBgKey;
+    const float b1 = (float)(double)e1 / r.fA;
+    const float b2 = (float)(double)e2 / r.fA;
+    const float z = (r.z[0] + b1 * (r.z[1] - r.z[0])) + b2 * (r.z[2] - r.z[0]);
+    if (!(z >= 0.0f && z <= 1.0f)) return kBgKey;
+    const unsigned bits = __float_as_uint(z) & 0x7FFFFFFFu;
+    return ((unsigned long long)bits << 32) | r.tri;
+}
+
+constexpr int kRasterThreads = 256;
+
+// One workgroup per tile; each thread owns T*T/256 (or one) pixels and keeps
+// the minimum key in registers while the tile's bin streams through LDS.
+template <int T>
+__global__ __launch_bounds__(kRasterThreads) void raster_kernel(
+    const ViewConst *__restrict__ views, const int *__restrict__ tile_view, const TriSetup *__restrict__ setup,
+    const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
+    unsigned long long *__restrict__ keys) {
+    constexpr int NPIX = T * T;
+    constexpr int NT = NPIX < kRasterThreads ? NPIX : kRasterThreads;
+    constexpr int PPT = NPIX / NT;
+    __shared__ RasterTri tris[NT];
+    const int gt = blockIdx.x;
+    const int view = tile_view[gt];
+    const ViewConst &v = views[view];
+    const int lt = gt - v.tile_off;
+    const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
+    const int tid = threadIdx.x;
+    if (tid >= NT) return;
+    int pi[PPT], pj[PPT];
+    unsigned long long best[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int l = tid + k * NT;
+        pi[k] = tx * T + (l % T);
+        pj[k] = ty * T + (l / T);
+        best[k] = kBgKey;
+    }
+    const unsigned b0 = tile_start[gt], b1 = tile_start[gt + 1];
+    for (unsigned c = b0; c < b1; c += NT) {
+        const unsigned n = min((unsigned)NT, b1 - c);
+        __syncthreads();
+        if ((unsigned)tid < n) {
+            const unsigned si = bins[c + tid];
+            tris[tid] = load_raster_tri(setup[si], si - (unsigned)v.setup_off);
+        }
+        __syncthreads();
+        for (unsigned q = 0; q < n; ++q) {
+            const RasterTri &r = tris[q];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const unsigned long long key = sample_key(r, pi[k], pj[k]);
+                best[k] = key < best[k] ? key : best[k];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (pi[k] < v.W && pj[k] < v.H) keys[v.pix_off + (long long)pj[k] * v.W + pi[k]] = best[k];
+}
+
+// Triangles that did not fit the bins: one workgroup per listed triangle at
+// a time, atomic minimum over its bounding box.
+__global__ void overflow_raster_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
+                                       const unsigned *__restrict__ list, const DevCounters *counters,
+                                       unsigned long long *__restrict__ keys) {
+    const unsigned n = counters->overflow_list_len;
+    for (unsigned o = blockIdx.x; o < n; o += gridDim.x) {
+        const unsigned si = list[o];
+        const TriSetup &s = setup[si];
+        const ViewConst &v = views[s.pad2[0]];
+        const RasterTri r = load_raster_tri(s, si - (unsigned)v.setup_off);
+        const int w = r.bx1 - r.bx0 + 1, h = r.by1 - r.by0 + 1;
+        if (w <= 0 || h <= 0) continue;
+        const long long npix = (long long)w * h;
+        for (long long q = threadIdx.x; q < npix; q += blockDim.x) {
+            const int i = r.bx0 + (int)(q % w), j = r.by0 + (int)(q / w);
+            const unsigned long long key = sample_key(r, i, j);
+            if (key != kBgKey) atomicMin(&keys[v.pix_off + (long long)j * v.W + i], key);
+        }
+    }
+}
+
+__global__ void overflow_count_kernel(DevCounters *counters) {
+    counters->overflow += counters->overflow_list_len;
+}
+
+// ----------------------------------------------------------------------------- host launchers
+
+hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, hipStream_t s) {
+    if (L == 0) return hipSuccess;
+    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_light_param_grad(const CamStatic *cams, const float *params, const float *glight, float *gparams,
+                                   int L, hipStream_t s) {
+    if (L == 0) return hipSuccess;
+    hipLaunchKernelGGL(light_param_grad_kernel, dim3((L + 63) / 64), dim3(64), 0, s, cams, params, glight, gparams, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
+                            hipStream_t s) {
+    if (nviews == 0 || max_verts == 0) return hipSuccess;
+    hipLaunchKernelGGL(transform_kernel, dim3((max_verts + 255) / 256, nviews), dim3(256), 0, s, views, verts, clip);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const int *faces, const float4 *clip,
+                        TriSetup *setup, unsigned *pair_count, int tile, DevCounters *counters, hipStream_t s) {
+    if (nviews == 0 || max_faces == 0) return hipSuccess;
+    hipLaunchKernelGGL(setup_kernel, dim3((max_faces + 255) / 256, nviews), dim3(256), 0, s, views, faces, clip,
+                       setup, pair_count, tile, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,
+                          unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
+                          unsigned *tile_cursor, unsigned *scan_scratch, int ntiles, unsigned *bins,
+                          unsigned *overflow_list, DevCounters *counters, hipStream_t s) {
+    const int grid = 2048;
+    hipLaunchKernelGGL(pairs_total_kernel, dim3(1), dim3(1), 0, s, pair_off, ntri, counters);
+    hipLaunchKernelGGL(bin_kernel<false>, dim3(grid), dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
+                       tile_count, (const unsigned *)nullptr, (unsigned *)nullptr);
+    hipError_t e = launch_scan(tile_count, tile_start, scan_scratch, ntiles, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_kernel<true>, dim3(grid), dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
+                       tile_cursor, (const unsigned *)tile_start, bins);
+    if (ntri > 0)
+        hipLaunchKernelGGL(overflow_list_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
+                           overflow_list, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntiles, int tile, const TriSetup *setup,
+                         const unsigned *tile_start, const unsigned *bins, const unsigned *overflow_list,
+                         const DevCounters *counters_ro, DevCounters *counters, unsigned long long *keys,
+                         hipStream_t s) {
+    if (ntiles > 0) {
+        if (tile == 8)
+            hipLaunchKernelGGL(raster_kernel<8>, dim3(ntiles), dim3(64), 0, s, views, tile_view, setup, tile_start,
+                               bins, keys);
+        else if (tile == 16)
+            hipLaunchKernelGGL(raster_kernel<16>, dim3(ntiles), dim3(256), 0, s, views, tile_view, setup, tile_start,
+                               bins, keys);
+        else
+            hipLaunchKernelGGL(raster_kernel<32>, dim3(ntiles), dim3(256), 0, s, views, tile_view, setup, tile_start,
+                               bins, keys);
+    }
+    hipLaunchKernelGGL(overflow_raster_kernel, dim3(512), dim3(256), 0, s, views, setup, overflow_list, counters_ro,
+                       keys);
+    hipLaunchKernelGGL(overflow_count_kernel, dim3(1), dim3(1), 0, s, counters);
+    return hipGetLastError();
+}
+
+}  // namespace dsm

@@ -1,0 +1,273 @@
+// Forward shading kernels: moment resolve of the light views, edge smoothing
+// (light maps and camera images), and the deferred Chebyshev + Lambert pass.
+//
+// Moment resolve (Alg. 1, RenderScene): for each shadow-map texel the world
+// point x on the nearest triangle is recovered from perspective-correct
+// barycentrics (the point of the triangle that projects to the texel
+// centre), its distance d(x) to the light (Sec. 3: Euclidean for point and
+// spot lights, from a plane outside the scene for directional lights) is
+// normalized, z = d / far, and (z, z^2) is written; texels without a triangle
+// hold the far value (1, 1).
+//
+// Lookup (Alg. 2, ComputeVisibility, and Lambert shading summed over lights):
+// per camera pixel the world point x and face normal n are recovered the same
+// way; per light u = L(x), (m1, m2) is fetched bilinearly (clamp-to-edge),
+// sigma^2 = max(m2 - m1^2, min_variance), v = 1 if z <= m1 else
+// sigma^2 / (sigma^2 + (z - m1)^2) (one-sided Chebyshev, Sec. 3); points outside
+// the light frustum count as lit; colour = albedo * sum_l max(0, n.omega_l)
+// v_l I_l cone_l.
+#include "aa.h"
+#include "dsm_internal.h"
+
+namespace dsm {
+
+struct Bary {
+    float b0, b1, b2;
+};
+
+// Barycentrics of the point of triangle (c0, c1, c2) that projects to NDC
+// (px, py): sum b_i (x_i - px w_i) = 0, sum b_i (y_i - py w_i) = 0, sum b_i = 1.
+__device__ __forceinline__ Bary persp_bary(float4 c0, float4 c1, float4 c2, float px, float py) {
+    const float a0x = c0.x - px * c0.w, a0y = c0.y - py * c0.w;
+    const float a1x = c1.x - px * c1.w, a1y = c1.y - py * c1.w;
+    const float a2x = c2.x - px * c2.w, a2y = c2.y - py * c2.w;
+    const float k0 = a1x * a2y - a1y * a2x;
+    const float k1 = a2x * a0y - a2y * a0x;
+    const float k2 = a0x * a1y - a0y * a1x;
+    const float s = k0 + k1 + k2;
+    return Bary{k0 / s, k1 / s, k2 / s};
+}
+
+__device__ __forceinline__ float ndc_centre(int i, int n) { return (float)(2 * i + 1) / (float)n - 1.0f; }
+
+__device__ __forceinline__ float light_depth(const ViewConst &l, float x, float y, float z) {
+    float d;
+    if (l.kind == kDirectional) {
+        d = ((x - l.pos[0]) * l.dir[0] + (y - l.pos[1]) * l.dir[1]) + (z - l.pos[2]) * l.dir[2];
+    } else {
+        const float dx = x - l.pos[0], dy = y - l.pos[1], dz = z - l.pos[2];
+        d = sqrtf((dx * dx + dy * dy) + dz * dz);
+    }
+    return d / l.zfar;
+}
+
+// ----------------------------------------------------------------------------- resolve
+
+__global__ void resolve_kernel(const ViewConst *__restrict__ views, const int *__restrict__ faces,
+                               const float *__restrict__ verts, const float4 *__restrict__ clip,
+                               const unsigned long long *__restrict__ keys, float *__restrict__ F0) {
+    const ViewConst &l = views[blockIdx.y];
+    const int S = l.W;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S * S) return;
+    const unsigned long long key = keys[l.pix_off + t];
+    float z = 1.0f, z2 = 1.0f;
+    if (key != kBgKey) {
+        const int tri = (int)(unsigned)key;
+        const int *f = faces + 3 * (size_t)(l.face_off + tri);
+        const int i = t % S, j = t / S;
+        const float px = ndc_centre(i, S), py = -ndc_centre(j, S);
+        const float4 c0 = clip[l.clip_off + f[0]], c1 = clip[l.clip_off + f[1]], c2 = clip[l.clip_off + f[2]];
+        const Bary b = persp_bary(c0, c1, c2, px, py);
+        const float *v0 = verts + 3 * (size_t)(l.vert_off + f[0]);
+        const float *v1 = verts + 3 * (size_t)(l.vert_off + f[1]);
+        const float *v2 = verts + 3 * (size_t)(l.vert_off + f[2]);
+        const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
+        const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
+        const float zz = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
+        z = light_depth(l, x, y, zz);
+        z2 = z * z;
+    }
+    F0[l.map_off + t] = z;
+    F0[l.map_off + (long long)S * S + t] = z2;
+}
+
+// ----------------------------------------------------------------------------- smoothing forward
+
+// Light maps: planar 2-channel; grid.y = light view.  Camera images:
+// interleaved C channels; grid.y = render (view = that render's camera).
+template <bool LIGHT>
+__global__ void aa_forward_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
+                                  const TriSetup *__restrict__ setup, const int *__restrict__ faces,
+                                  const int *__restrict__ adj, const float *__restrict__ verts,
+                                  const unsigned long long *__restrict__ keys, const float *__restrict__ src,
+                                  float *__restrict__ dst, int C) {
+    const ViewConst &v = LIGHT ? views[blockIdx.y] : views[renders[blockIdx.y].camera_view];
+    const int W = v.W, H = v.H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= W * H) return;
+    const long long base = LIGHT ? v.map_off : renders[blockIdx.y].img_off;
+    const long long cstride = LIGHT ? (long long)W * H : 1;
+    const int pstride = LIGHT ? 1 : C;
+    const int i = p % W, j = p / W;
+    const unsigned long long *kv = keys + v.pix_off;
+    const unsigned long long ks = kv[p];
+    float acc[3];
+    for (int c = 0; c < C; ++c) acc[c] = src[base + (long long)p * pstride + c * cstride];
+    const float self[3] = {acc[0], C > 1 ? acc[1] : 0.f, C > 2 ? acc[2] : 0.f};
+    const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+    if (v.antialias) {
+        for (int d = 0; d < 4; ++d) {
+            const int in_ = i + di[d], jn = j + dj[d];
+            if (in_ < 0 || in_ >= W || jn < 0 || jn >= H) continue;
+            const int q = jn * W + in_;
+            const unsigned long long kn = kv[q];
+            if ((unsigned)kn == (unsigned)ks) continue;
+            bool self_front;
+            AAPair pr;
+            if (!aa_eval<false>(v, setup, faces, adj, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
+            const bool self_recv = (pr.recv == 1) != self_front;   // receiver: other when recv==1
+            if (!self_recv) continue;
+            for (int c = 0; c < C; ++c) {
+                const float nv = src[base + (long long)q * pstride + c * cstride];
+                acc[c] += pr.w * (nv - self[c]);
+            }
+        }
+    }
+    for (int c = 0; c < C; ++c) dst[base + (long long)p * pstride + c * cstride] = acc[c];
+}
+
+// ----------------------------------------------------------------------------- lookup + shade
+
+struct Fetch {
+    float m1, m2;
+    int x0, x1, y0, y1;
+    float fx, fy;
+};
+
+__device__ __forceinline__ Fetch bilinear2(const float *__restrict__ maps, long long off, int S, float sx, float sy) {
+    Fetch f;
+    const float fx0 = floorf(sx), fy0 = floorf(sy);
+    f.fx = sx - fx0;
+    f.fy = sy - fy0;
+    const int ix = (int)fx0, iy = (int)fy0;
+    f.x0 = min(max(ix, 0), S - 1);
+    f.x1 = min(max(ix + 1, 0), S - 1);
+    f.y0 = min(max(iy, 0), S - 1);
+    f.y1 = min(max(iy + 1, 0), S - 1);
+    const float *a = maps + off, *b = maps + off + (long long)S * S;
+    const long long o00 = (long long)f.y0 * S + f.x0, o01 = (long long)f.y0 * S + f.x1;
+    const long long o10 = (long long)f.y1 * S + f.x0, o11 = (long long)f.y1 * S + f.x1;
+    const float w00 = (1.f - f.fx) * (1.f - f.fy), w01 = f.fx * (1.f - f.fy);
+    const float w10 = (1.f - f.fx) * f.fy, w11 = f.fx * f.fy;
+    f.m1 = ((w00 * a[o00] + w01 * a[o01]) + w10 * a[o10]) + w11 * a[o11];
+    f.m2 = ((w00 * b[o00] + w01 * b[o01]) + w10 * b[o10]) + w11 * b[o11];
+    return f;
+}
+
+__global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
+                              const int *__restrict__ render_lights, const int *__restrict__ faces,
+                              const float *__restrict__ verts, const float *__restrict__ albedo,
+                              const float4 *__restrict__ clip, const unsigned long long *__restrict__ keys,
+                              const float *__restrict__ maps, float *__restrict__ img0, int C) {
+    const RenderConst &R = renders[blockIdx.y];
+    const ViewConst &cv = views[R.camera_view];
+    const int W = cv.W, H = cv.H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= W * H) return;
+    const unsigned long long key = keys[cv.pix_off + p];
+    float *out = img0 + R.img_off + (long long)p * C;
+    if (key == kBgKey) {
+        for (int c = 0; c < C; ++c) out[c] = 0.f;
+        return;
+    }
+    const int tri = (int)(unsigned)key;
+    const int *f = faces + 3 * (size_t)(cv.face_off + tri);
+    const int i = p % W, j = p / W;
+    const float px = ndc_centre(i, W), py = -ndc_centre(j, H);
+    const float4 c0 = clip[cv.clip_off + f[0]], c1 = clip[cv.clip_off + f[1]], c2 = clip[cv.clip_off + f[2]];
+    const Bary b = persp_bary(c0, c1, c2, px, py);
+    const float *v0 = verts + 3 * (size_t)(cv.vert_off + f[0]);
+    const float *v1 = verts + 3 * (size_t)(cv.vert_off + f[1]);
+    const float *v2 = verts + 3 * (size_t)(cv.vert_off + f[2]);
+    const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
+    const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
+    const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
+    const float e1x = v1[0] - v0[0], e1y = v1[1] - v0[1], e1z = v1[2] - v0[2];
+    const float e2x = v2[0] - v0[0], e2y = v2[1] - v0[1], e2z = v2[2] - v0[2];
+    float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    const float nn = sqrtf((nx * nx + ny * ny) + nz * nz);
+    nx /= nn;
+    ny /= nn;
+    nz /= nn;
+    float shade = 0.f;
+    for (int q = 0; q < R.light_count; ++q) {
+        const ViewConst &l = views[render_lights[R.light_begin + q]];
+        const float *M = l.M;
+        const float cx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+        const float cy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
+        const float cw = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
+        float vis = 1.f;
+        const float ux = cx / cw, uy = cy / cw;
+        if (cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f) {
+            const int S = l.W;
+            const float sx = (ux + 1.f) * (0.5f * S) - 0.5f;
+            const float sy = (1.f - uy) * (0.5f * S) - 0.5f;
+            const Fetch m = bilinear2(maps, l.map_off, S, sx, sy);
+            const float zz = light_depth(l, x, y, z);
+            const float var = fmaxf(m.m2 - m.m1 * m.m1, l.min_var);
+            const float dd = zz - m.m1;
+            vis = (zz <= m.m1) ? 1.f : var / (var + dd * dd);
+        }
+        float ox, oy, oz;
+        if (l.kind == kDirectional) {
+            ox = -l.dir[0];
+            oy = -l.dir[1];
+            oz = -l.dir[2];
+        } else {
+            ox = l.pos[0] - x;
+            oy = l.pos[1] - y;
+            oz = l.pos[2] - z;
+            const float on = sqrtf((ox * ox + oy * oy) + oz * oz);
+            ox /= on;
+            oy /= on;
+            oz /= on;
+        }
+        const float lam = fmaxf((nx * ox + ny * oy) + nz * oz, 0.f);
+        float cone = 1.f;
+        if (l.kind == kSpot) {
+            // cos of the angle between x - p and the axis: (-omega) . axis
+            const float ca = -((ox * l.dir[0] + oy * l.dir[1]) + oz * l.dir[2]);
+            cone = ca >= l.cos_half ? 1.f : 0.f;
+        }
+        shade += lam * vis * l.intensity * cone;
+    }
+    const float *rho = albedo + (size_t)(cv.face_off + tri) * C;
+    for (int c = 0; c < C; ++c) out[c] = rho[c] * shade;
+}
+
+// ----------------------------------------------------------------------------- launchers
+
+hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const int *faces, const float *verts,
+                          const float4 *clip, const unsigned long long *keys, float *F0, hipStream_t s) {
+    if (L == 0) return hipSuccess;
+    hipLaunchKernelGGL(resolve_kernel, dim3((max_texels + 255) / 256, L), dim3(256), 0, s, views, faces, verts, clip,
+                       keys, F0);
+    return hipGetLastError();
+}
+
+hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
+                             const TriSetup *setup, const int *faces, const int *adj, const float *verts,
+                             const unsigned long long *keys, const float *src, float *dst, int C, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const dim3 grid((max_pix + 255) / 256, n);
+    if (light)
+        hipLaunchKernelGGL(aa_forward_kernel<true>, grid, dim3(256), 0, s, views, renders, setup, faces, adj, verts,
+                           keys, src, dst, 2);
+    else
+        hipLaunchKernelGGL(aa_forward_kernel<false>, grid, dim3(256), 0, s, views, renders, setup, faces, adj, verts,
+                           keys, src, dst, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
+                         const int *render_lights, const int *faces, const float *verts, const float *albedo,
+                         const float4 *clip, const unsigned long long *keys, const float *maps, float *img0, int C,
+                         hipStream_t s) {
+    if (R == 0) return hipSuccess;
+    hipLaunchKernelGGL(lookup_kernel, dim3((max_pix + 255) / 256, R), dim3(256), 0, s, views, renders, render_lights,
+                       faces, verts, albedo, clip, keys, maps, img0, C);
+    return hipGetLastError();
+}
+
+}  // namespace dsm

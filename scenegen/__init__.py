@@ -306,7 +306,7 @@ def config1(seed: int = 1) -> Batch:
                  target_light_params=[f32([1.3, 5, 1])])
 
 
-def blob_scene(i: int):
+def blob_scene(i: int, with_pose: bool = True):
     rng = np.random.default_rng([2, i])
     T = int(rng.integers(2000, 20001))
     n_lat = max(3, int(round(np.sqrt(T / 4.0))))
@@ -323,16 +323,21 @@ def blob_scene(i: int):
         w = w / np.linalg.norm(w)
         if -w[1] >= np.cos(np.radians(30.0)):
             break
-    sc = Scene(verts=v, faces=f, albedo=np.full((len(f), 1), 0.8, np.float32),
-               pose_count=len(bv), pose_center=f32([0, 1.2, 0]), pose=pose)
+    if with_pose:
+        sc = Scene(verts=v, faces=f, albedo=np.full((len(f), 1), 0.8, np.float32),
+                   pose_count=len(bv), pose_center=f32([0, 1.2, 0]), pose=pose)
+    else:   # blob placed at its rest position, no pose parameters
+        v = v.copy()
+        v[:len(bv)] += f32([0, 1.2, 0])
+        sc = Scene(verts=v, faces=f, albedo=np.full((len(f), 1), 0.8, np.float32))
     return sc, f32(w)
 
 
-def config2(n_scenes: int = 64, resolution: int = 512) -> Batch:
+def config2(n_scenes: int = 64, resolution: int = 512, with_pose: bool = True) -> Batch:
     """Batched pose estimation: blobs of 2k..20k triangles, one directional light each."""
     scenes, lights, cams, renders = [], [], [], []
     for i in range(n_scenes):
-        sc, w = blob_scene(i)
+        sc, w = blob_scene(i, with_pose)
         scenes.append(sc)
         lights.append(Light('directional', w, scene=i, resolution=resolution, filter='box', k=5,
                             up=_up_for(w)))
@@ -340,7 +345,7 @@ def config2(n_scenes: int = 64, resolution: int = 512) -> Batch:
                            width=resolution, height=resolution, scene=i))
         renders.append(Render(i, [i]))
     return Batch('batched_pose', scenes, lights, cams, renders, channels=1,
-                 target_poses=[np.zeros(6, np.float32) for _ in scenes])
+                 target_poses=[np.zeros(6, np.float32) for _ in scenes] if with_pose else None)
 
 
 def config3(n_lat: int = 158, sm_res: int = 1024, view_res: int = 512,

@@ -1,0 +1,48 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/dsm.h declares, and argument validation
+rejects bad input before anything reaches the device."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, 'include', 'dsm.h')).read()
+    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+    return sorted(set(re.findall(r'\b(dsm_[a-z_0-9]+)\s*\(', text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2308_10896_amd import _lib
+    lib = _lib.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(_lib._SIGNATURES), set(names) ^ set(_lib._SIGNATURES)
+
+
+def test_version_and_status_strings():
+    from paper_2308_10896_amd import _lib
+    lib = _lib.lib()
+    assert b'gfx950' in lib.dsm_version()
+    for s in range(8):
+        assert lib.dsm_status_string(s)
+
+
+def test_filter_validation_on_host():
+    from paper_2308_10896_amd import _lib
+    lib = _lib.lib()
+    # even k, k > S, k > 31, negative count: rejected before any device call
+    assert lib.dsm_filter_moments(16, 1, 0, 4, 0.0, 1, 2, 0, None) == 1
+    assert lib.dsm_filter_moments(4, 1, 0, 5, 0.0, 1, 2, 0, None) == 1
+    assert lib.dsm_filter_moments(64, 1, 0, 33, 0.0, 1, 2, 0, None) == 1
+    assert lib.dsm_filter_moments(64, -1, 0, 5, 0.0, 1, 2, 0, None) == 1
+    assert lib.dsm_filter_moments(64, 1, 7, 5, 0.0, 1, 2, 0, None) == 1
+    # null pointers
+    assert lib.dsm_filter_moments(64, 1, 0, 5, 0.0, None, 2, 0, None) == 1
+    # zero maps is a no-op
+    assert lib.dsm_filter_moments(64, 0, 0, 5, 0.0, None, None, 0, None) == 0

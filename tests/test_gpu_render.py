@@ -1,0 +1,119 @@
+"""GPU parity of the full forward pass (raster keys bit-exact; moments,
+smoothed and filtered maps, shaded images within tolerance) and of the
+backward pass (gradients w.r.t. vertices, light parameters, albedo, pose)
+against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from parity_helpers import (IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous, gpu_run,
+                            loss_grad, normwise, oracle_run, random_grad)
+
+pytestmark = pytest.mark.gpu
+
+
+def cfg0_ragged():
+    b = sg.config0()
+    b.lights[0].resolution = 200
+    b.cameras[0].width, b.cameras[0].height = 250, 190
+    return b
+
+
+def cfg1_small():
+    b = sg.config1()
+    b.lights[0].resolution = 300
+    b.cameras[0].width, b.cameras[0].height = 280, 232
+    return b
+
+
+def cfg2_small(n=3, res=176, with_pose=False):
+    return sg.config2(n_scenes=n, resolution=res, with_pose=with_pose)
+
+
+BATCHES = {'cfg0': sg.config0, 'cfg0_ragged': cfg0_ragged, 'cfg1_small': cfg1_small, 'cfg2_small': cfg2_small}
+
+
+def check_forward(b, g, o):
+    for v, (kg, ko) in enumerate(zip(g['keys'], o['keys'])):
+        assert kg.shape == ko.shape
+        diff = kg != ko
+        assert not diff.any(), f'view {v}: {int(diff.sum())} keys differ'
+    for l in range(len(b.lights)):
+        assert_close(f'F0[{l}]', g['F0'][l], o['F0'][l], MAP_RTOL, MAP_ATOL)
+        assert_close(f'F1[{l}]', g['F1'][l], o['F1'][l], MAP_RTOL, MAP_ATOL)
+        assert_close(f'M[{l}]', g['M'][l], o['M'][l], MAP_RTOL, MAP_ATOL)
+    for r in range(len(b.renders)):
+        ok = ~cone_ambiguous(b, o, r)[..., None]
+        assert_close(f'img0[{r}]', g['img0'][r], o['img0'][r], IMG_RTOL, IMG_ATOL, mask=ok)
+        assert_close(f'image[{r}]', g['images'][r], o['images'][r], IMG_RTOL, IMG_ATOL, mask=ok)
+    assert g['stats']['culled'] == 0 and o['culled'] == 0
+    assert g['stats']['bad_indices'] == 0
+
+
+@pytest.mark.parametrize('name', list(BATCHES))
+def test_forward_matches_oracle(name):
+    b = BATCHES[name]()
+    g = gpu_run(b)
+    o = oracle_run(b)
+    check_forward(b, g, o)
+
+
+@pytest.mark.parametrize('tile,bins', [(8, 0), (32, 0), (16, 1)])
+def test_keys_independent_of_tile_and_bin_capacity(tile, bins):
+    """Tile size and bin capacity (1 pair per triangle forces most triangles
+    through the overflow path) must not change a single key."""
+    b = cfg2_small(2, 160)
+    ref = gpu_run(b)
+    g = gpu_run(b, tile_size=tile, bin_scale=bins)
+    for kr, kg in zip(ref['keys'], g['keys']):
+        assert np.array_equal(kr, kg)
+    for a, c in zip(ref['images'], g['images']):
+        assert np.array_equal(a, c)
+    if bins == 1:
+        assert g['stats']['overflow'] > 0
+
+
+def test_run_twice_bit_identical_forward():
+    b = cfg1_small()
+    a = gpu_run(b)
+    c = gpu_run(b)
+    for x, y in zip(a['keys'], c['keys']):
+        assert np.array_equal(x, y)
+    for x, y in zip(a['images'], c['images']):
+        assert np.array_equal(x, y)
+
+
+GRAD_TOL = 1e-3
+
+
+@pytest.mark.parametrize('name', ['cfg0', 'cfg0_ragged', 'cfg1_small'])
+def test_backward_matches_oracle_loss_gradient(name):
+    b = BATCHES[name]()
+    o0 = oracle_run(b)
+    G = loss_grad(b, o0['images'])
+    g = gpu_run(b, grad_images=G)
+    o = oracle_run(b, grad_images=G)
+    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
+    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
+    normwise('galbedo', g['galbedo'], o['galbedo'], GRAD_TOL)
+
+
+def test_backward_random_cotangent_cfg0():
+    b = sg.config0()
+    G = random_grad(b, 3)
+    g = gpu_run(b, grad_images=G)
+    o = oracle_run(b, grad_images=G)
+    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
+    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
+    normwise('galbedo', g['galbedo'], o['galbedo'], GRAD_TOL)
+
+
+def test_pose_forward_and_backward():
+    b = cfg2_small(2, 160, with_pose=True)
+    o0 = oracle_run(b, pose=True)
+    G = loss_grad(b, o0['images'])
+    g = gpu_run(b, grad_images=G, pose=True)
+    o = oracle_run(b, grad_images=G, pose=True)
+    check_forward(b, g, o)
+    normwise('gpose', g['gpose'], o['gpose'], GRAD_TOL)
+    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
