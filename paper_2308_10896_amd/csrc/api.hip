@@ -75,7 +75,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
                                       dsm_plan **out_plan) {
     if (!d || !out_plan) return DSM_ERR_INVALID_ARG;
     *out_plan = nullptr;
-    if (tile_size == 0) tile_size = 16;
+    if (tile_size == 0) tile_size = 8;
     if (tile_size != 8 && tile_size != 16 && tile_size != 32) return DSM_ERR_INVALID_ARG;
     if (bin_capacity_scale == 0) bin_capacity_scale = 32;
     if (bin_capacity_scale < 0 || bin_capacity_scale > 1024) return DSM_ERR_INVALID_ARG;
@@ -143,10 +143,14 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->pose_centers.assign(3 * (size_t)B, 0.f);
     if (d->pose_counts) p->pose_counts.assign(d->pose_counts, d->pose_counts + B);
     if (d->pose_centers) p->pose_centers.assign(d->pose_centers, d->pose_centers + 3 * (size_t)B);
-    for (int b = 0; b < B; ++b) p->max_pose_verts = std::max(p->max_pose_verts, p->pose_counts[b]);
+    for (int b = 0; b < B; ++b) {
+        p->max_pose_verts = std::max(p->max_pose_verts, p->pose_counts[b]);
+        p->max_scene_verts = std::max(p->max_scene_verts, p->vert_off[b + 1] - p->vert_off[b]);
+        p->max_scene_faces = std::max(p->max_scene_faces, p->face_off[b + 1] - p->face_off[b]);
+    }
 
     // views: lights then cameras
-    long long clip = 0, tri = 0, pix = 0, maps = 0, tiles = 0;
+    long long clip = 0, tri = 0, pix = 0, maps = 0, tiles = 0, part_light = 0, part_gm = 0, part_render = 0;
     auto add_view = [&](ViewConst &v, int scene, int W, int H) {
         v.scene = scene;
         v.W = W;
@@ -183,7 +187,12 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         add_view(v, x.scene, x.resolution, x.resolution);
         v.map_off = maps;
         maps += 2LL * x.resolution * x.resolution;
+        v.part_off = (int)part_light;
+        part_light += (long long)v.tiles_x * v.tiles_y;
+        v.part_gm_off = (int)part_gm;
+        part_gm += (v.nverts + 255) / 256;
         p->max_light_texels = std::max(p->max_light_texels, x.resolution * x.resolution);
+        p->max_light_tiles = std::max(p->max_light_tiles, v.tiles_x * v.tiles_y);
         p->views_h[l] = v;
         CamStatic &cs = p->light_cams_h[l];
         memset(&cs, 0, sizeof(cs));
@@ -218,6 +227,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         view_projection<double>(cs, eye, tg, M);
         for (int i = 0; i < 16; ++i) v.M[i] = (float)M[i];
         p->max_cam_pix = std::max(p->max_cam_pix, x.width * x.height);
+        p->max_cam_tiles = std::max(p->max_cam_tiles, v.tiles_x * v.tiles_y);
         p->views_h[L + c] = v;
     }
     long long img = 0;
@@ -229,10 +239,13 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         rc.camera_view = L + x.camera;
         rc.light_begin = x.light_begin;
         rc.light_count = x.light_count;
+        p->max_lights_per_render = std::max(p->max_lights_per_render, x.light_count);
         rc.W = d->cameras[x.camera].width;
         rc.H = d->cameras[x.camera].height;
         rc.img_off = img;
         rc.pix_off = p->views_h[L + x.camera].pix_off;
+        rc.part_off = (int)part_render;
+        part_render += 22LL * x.light_count * p->views_h[L + x.camera].tiles_x * p->views_h[L + x.camera].tiles_y;
         img += (long long)rc.W * rc.H * p->C;
         p->renders_h[r] = rc;
     }
@@ -291,11 +304,18 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_F1 = o; o = align_up(o + 4 * (size_t)maps);
     p->sc_gimg0 = o; o = align_up(o + 4 * (size_t)img);
+    p->sc_bigcount = o; o = align_up(o + 64);
     p->sc_gM = o; o = align_up(o + 4 * (size_t)maps);
     p->sc_gclip = o; o = align_up(o + 16 * (size_t)clip);
+    p->sc_zero_bwd_end = o;
     p->sc_glight = o; o = align_up(o + 4 * 24 * (size_t)std::max(L, 1));
-    p->sc_galbedo = o; o = align_up(o + 4 * (size_t)Ft * p->C);
     p->sc_gF1 = o; o = align_up(o + 4 * (size_t)maps);
+    p->sc_pair_sums = o; o = align_up(o + 4 * 21 * (size_t)p->capacity);
+    p->sc_gtri = o; o = align_up(o + 4 * 21 * ((size_t)tri + 1));
+    p->sc_biglist = o; o = align_up(o + 4 * ((size_t)tri + 1));
+    p->sc_part_light = o; o = align_up(o + 4 * 6 * (size_t)(part_light + 1));
+    p->sc_part_gm = o; o = align_up(o + 4 * 16 * (size_t)(part_gm + 1));
+    p->sc_part_render = o; o = align_up(o + 4 * (size_t)(part_render + 1));
     p->scratch_bytes = o;
 
     // device uploads
@@ -308,7 +328,50 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         const ViewConst &x = p->views_h[v];
         for (int t = 0; t < x.tiles_x * x.tiles_y; ++t) tile_view[x.tile_off + t] = v;
     }
+    // backward gather lists
+    std::vector<int> cam_off(Cm + 1, 0), cam_list;
+    for (int c = 0; c < Cm; ++c) {
+        for (int r = 0; r < R; ++r)
+            if (d->renders[r].camera == c) cam_list.push_back(r);
+        cam_off[c + 1] = (int)cam_list.size();
+    }
+    std::vector<int> sv_off(B + 1, 0), sv_list;
+    for (int b = 0; b < B; ++b) {
+        for (int v = 0; v < p->nviews; ++v)
+            if (p->views_h[v].scene == b) sv_list.push_back(v);
+        sv_off[b + 1] = (int)sv_list.size();
+    }
+    std::vector<int> vc_off(Vt + 1, 0), vc_list(3 * (size_t)Ft);
+    for (int b = 0; b < B; ++b)
+        for (long long f = p->face_off[b]; f < p->face_off[b + 1]; ++f)
+            for (int k = 0; k < 3; ++k) vc_off[p->vert_off[b] + d->faces[3 * f + k] + 1]++;
+    for (long long v = 0; v < Vt; ++v) vc_off[v + 1] += vc_off[v];
+    {
+        std::vector<int> fill(vc_off.begin(), vc_off.end() - 1);
+        for (int b = 0; b < B; ++b)
+            for (long long f = p->face_off[b]; f < p->face_off[b + 1]; ++f)
+                for (int k = 0; k < 3; ++k) {
+                    const long long gv = p->vert_off[b] + d->faces[3 * f + k];
+                    vc_list[fill[gv]++] = (int)((f - p->face_off[b]) << 2) | k;
+                }
+    }
+    std::vector<int> lr_off(L + 1, 0), lr_list;
+    for (int l = 0; l < L; ++l) {
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < d->renders[r].light_count; ++q)
+                if (d->render_light_list[d->renders[r].light_begin + q] == l) lr_list.push_back((r << 5) | q);
+        lr_off[l + 1] = (int)lr_list.size();
+    }
     dsm_status st = DSM_OK;
+    if (st == DSM_OK) st = upload(&p->cam_renders_off_d, cam_off.data(), cam_off.size());
+    if (st == DSM_OK) st = upload(&p->cam_renders_d, cam_list.data(), cam_list.size());
+    if (st == DSM_OK) st = upload(&p->scene_views_off_d, sv_off.data(), sv_off.size());
+    if (st == DSM_OK) st = upload(&p->scene_views_d, sv_list.data(), sv_list.size());
+    if (st == DSM_OK) st = upload(&p->vc_off_d, vc_off.data(), vc_off.size());
+    if (st == DSM_OK) st = upload(&p->vc_list_d, vc_list.data(), vc_list.size());
+    if (st == DSM_OK) st = upload(&p->light_renders_off_d, lr_off.data(), lr_off.size());
+    if (st == DSM_OK) st = upload(&p->light_renders_d, lr_list.data(), lr_list.size());
+    if (st == DSM_OK) st = upload(&p->scene_face_off_d, p->face_off.data(), p->face_off.size());
     if (st == DSM_OK) st = upload(&p->views_d, p->views_h.data(), p->views_h.size());
     if (st == DSM_OK) st = upload(&p->light_cams_d, p->light_cams_h.data(), p->light_cams_h.size());
     if (st == DSM_OK) st = upload(&p->renders_d, p->renders_h.data(), p->renders_h.size());
@@ -333,7 +396,9 @@ extern "C" void dsm_plan_destroy(dsm_plan *p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *bufs[] = {p->views_d, p->light_cams_d, p->renders_d, p->render_lights_d, p->faces_d, p->adj_d,
-                    p->tile_view_d, p->blur_jobs_d, p->scene_vert_off_d, p->pose_counts_d, p->pose_centers_d};
+                    p->tile_view_d, p->blur_jobs_d, p->scene_vert_off_d, p->pose_counts_d, p->pose_centers_d,
+                    p->cam_renders_off_d, p->cam_renders_d, p->scene_views_off_d, p->scene_views_d, p->vc_off_d,
+                    p->vc_list_d, p->light_renders_off_d, p->light_renders_d, p->scene_face_off_d};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -412,25 +477,43 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     const float *F0 = at<float>(saved, p->sv_F0);
     const float *Mm = at<float>(saved, p->sv_M);
     const float *img0 = at<float>(saved, p->sv_img0);
+    const DevCounters *cnt = at<DevCounters>(scratch, p->sc_counters);
+    const unsigned *pair_off = at<unsigned>(scratch, p->sc_pair_off);
+    const unsigned *tile_start = at<unsigned>(scratch, p->sc_tile_start);
+    const unsigned *bins = at<unsigned>(scratch, p->sc_bins);
+    const unsigned *overflow = at<unsigned>(scratch, p->sc_overflow);
     float *gimg0 = at<float>(scratch, p->sc_gimg0);
+    unsigned *big_count = at<unsigned>(scratch, p->sc_bigcount);
     float *gM = at<float>(scratch, p->sc_gM);
     float4 *gclip = at<float4>(scratch, p->sc_gclip);
     float *glight = at<float>(scratch, p->sc_glight);
-    float *galb = galbedo ? galbedo : at<float>(scratch, p->sc_galbedo);
     float *gF1 = at<float>(scratch, p->sc_gF1);
+    float *pair_sums = at<float>(scratch, p->sc_pair_sums);
+    float *gtri = at<float>(scratch, p->sc_gtri);
+    unsigned *big_list = at<unsigned>(scratch, p->sc_biglist);
+    float *part_light = at<float>(scratch, p->sc_part_light);
+    float *part_gm = at<float>(scratch, p->sc_part_gm);
+    float *part_render = at<float>(scratch, p->sc_part_render);
 
-    DSM_TRY(zero_async(gM, p->sc_gF1 - p->sc_gM, s));   // gM, gclip, glight, scratch galbedo
-    DSM_TRY(zero_async(gverts, 12 * (size_t)p->V_total, s));
-    if (galbedo) DSM_TRY(zero_async(galbedo, 4 * (size_t)p->F_total * p->C, s));
+    DSM_TRY(zero_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, s));   // big count, gM, silhouette gclip
+    DSM_TRY(launch_overflow_rows_zero(overflow, cnt, gtri, s));
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
     DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, p->adj_d,
                                       verts, keys, img0, gimg, gimg0, gclip, p->C, s));
-    DSM_TRY(launch_lookup_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, p->render_lights_d, p->faces_d,
-                                   verts, albedo, clip, keys, Mm, gimg0, gM, gverts, gclip, glight, galb, p->C, s));
+    DSM_TRY(launch_lookup_backward(p->tile, p->views_d, p->L, p->Cm, p->max_cam_tiles, p->max_lights_per_render,
+                                   p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
+                                   p->faces_d, verts, albedo, clip, keys, Mm, gimg0, gM, setup, tile_start, bins,
+                                   pair_off, pair_sums, gtri, part_render, p->C, s));
     DSM_TRY(launch_blur(p->blur_jobs_d, p->L, p->blur_tiles, gM, gF1, true, p->blur_rmax, s));
-    DSM_TRY(launch_light_backward(p->views_d, p->L, p->max_light_texels, setup, p->faces_d, p->adj_d, verts, clip,
-                                  keys, F0, gF1, gverts, gclip, glight, s));
-    DSM_TRY(launch_transform_backward(p->views_d, p->nviews, p->L, p->max_verts, verts, gclip, gverts, glight, s));
+    DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, p->adj_d, verts,
+                                  clip, keys, F0, gF1, gclip, tile_start, bins, pair_off, pair_sums, gtri, part_light,
+                                  s));
+    DSM_TRY(launch_vertex_gradients(p->views_d, p->L, p->B, p->max_scene_verts, p->max_scene_faces, p->ntri,
+                                    p->capacity, p->scene_vert_off_d, p->scene_face_off_d, p->scene_views_off_d,
+                                    p->scene_views_d, p->vc_off_d, p->vc_list_d, pair_off, pair_sums, gtri, big_list,
+                                    big_count, verts, gclip, gverts, part_gm, galbedo, p->C, s));
+    DSM_TRY(launch_glight_reduce(p->views_d, p->L, p->renders_d, p->light_renders_off_d, p->light_renders_d, part_gm,
+                                 part_light, part_render, glight, s));
     DSM_TRY(launch_light_param_grad(p->light_cams_d, lparams, glight, glparams, p->L, s));
     return DSM_OK;
 }

@@ -38,7 +38,8 @@ struct ViewConst {
     int tiles_x, tiles_y;
     int antialias;
     long long map_off;  // light views: first texel of the 2-channel maps (plane stride S*S)
-    int pad[2];
+    int part_off;       // light views: first per-tile slot of the backward light-frame partials
+    int part_gm_off;    // light views: first per-vertex-block slot of the dL/dM partials
 };
 
 struct RenderConst {
@@ -46,7 +47,7 @@ struct RenderConst {
     int light_begin;    // range into the device list of light view indices
     int light_count;
     int W, H;
-    int pad;
+    int part_off;       // first float of this render's per-(light, tile) backward partials
     long long img_off;  // first float of the [H,W,C] image
     long long pix_off;  // camera view's first sample (keys)
 };
@@ -141,17 +142,28 @@ hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *
                                      const TriSetup *setup, const int *faces, const int *adj, const float *verts,
                                      const unsigned long long *keys, const float *img0, const float *gimg,
                                      float *gimg0, float4 *gclip, int C, hipStream_t s);
-hipError_t launch_lookup_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
-                                  const int *render_lights, const int *faces, const float *verts,
-                                  const float *albedo, const float4 *clip, const unsigned long long *keys,
-                                  const float *maps, const float *gimg0, float *gmaps, float *gverts,
-                                  float4 *gclip, float *glight, float *galbedo, int C, hipStream_t s);
-hipError_t launch_light_backward(const ViewConst *views, int L, int max_texels, const TriSetup *setup,
+hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int Cm, int max_tiles, int max_lights,
+                                  const RenderConst *renders, const int *cam_renders_off, const int *cam_renders,
+                                  const int *render_lights, const int *faces, const float *verts, const float *albedo,
+                                  const float4 *clip, const unsigned long long *keys, const float *maps,
+                                  const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
+                                  const unsigned *bins, const unsigned *pair_off, float *pair_sums, float *gtri,
+                                  float *part_render, int C, hipStream_t s);
+hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const int *adj, const float *verts, const float4 *clip,
-                                 const unsigned long long *keys, const float *F0, const float *gF1, float *gverts,
-                                 float4 *gclip, float *glight, hipStream_t s);
-hipError_t launch_transform_backward(const ViewConst *views, int nviews, int L, int max_verts, const float *verts,
-                                     const float4 *gclip, float *gverts, float *glight, hipStream_t s);
+                                 const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
+                                 const unsigned *tile_start, const unsigned *bins, const unsigned *pair_off,
+                                 float *pair_sums, float *gtri, float *part_light, hipStream_t s);
+hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max_verts, int max_faces, int ntri,
+                                   unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
+                                   const int *scene_views_off, const int *scene_views, const int *vc_off,
+                                   const int *vc_list, const unsigned *pair_off, const float *pair_sums, float *gtri,
+                                   unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
+                                   float *gverts, float *part_gm, float *galbedo, int C, hipStream_t s);
+hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *counters, float *gtri, hipStream_t s);
+hipError_t launch_glight_reduce(const ViewConst *views, int L, const RenderConst *renders,
+                                const int *light_renders_off, const int *light_renders, const float *part_gm,
+                                const float *part_light, const float *part_render, float *glight, hipStream_t s);
 hipError_t launch_pose(const int *scene_vert_off, const int *pose_counts, const float *pose_centers, int B,
                        int max_verts, const float *local, const float *poses, float *world, hipStream_t s);
 hipError_t launch_pose_backward(const int *scene_vert_off, const int *pose_counts, int B, int max_verts,

@@ -16,9 +16,8 @@
 //   light smoothing^T + resolve^T (fused per texel)
 //   transform^T           : dL/dclip -> dL/dvertices (M^T) and dL/dM
 //
-// Vertex-indexed gradients are scattered with atomics after a wavefront
-// reduction over lanes that share a triangle (most lanes of a wave do), so a
-// ground plane covered by two triangles costs one atomic per wave, not 64.
+// Vertex-indexed gradients are reduced per (tile, triangle) before they reach
+// global memory (see "tile accumulation" below).
 #include "aa.h"
 #include "dsm_internal.h"
 #include "frames.h"
@@ -147,41 +146,147 @@ __global__ __launch_bounds__(256) void aa_camera_backward_kernel(
     for (int c = 0; c < C; ++c) gimg0[R.img_off + (long long)p * C + c] = acc[c];
 }
 
+// ----------------------------------------------------------------------------- reduction by (triangle, tile)
+
+// Float atomics on this GPU are performed at the memory side, so many
+// workgroups adding into the same few addresses (the two triangles of a
+// ground plane, a light's frame gradient) serialize.  The backward kernels
+// therefore avoid hot atomics altogether: they walk the same tiles as the
+// rasterizer and, for every triangle binned to a tile, write the sum of that
+// triangle's per-pixel gradient terms over the tile's pixels into the
+// triangle's slot for that tile (the binning already gave every (triangle,
+// tile) pair a unique index).  Later gathers sum those slots per triangle,
+// then per vertex (through the vertex -> triangle-corner lists), with plain
+// stores.  Per-light terms are written per tile and summed per light the
+// same way.  Only triangles that overflowed the bins, the sparse silhouette
+// terms and the bilinear moment-map scatter use atomics.
+constexpr int kNV = 21;   // per pair: 9 world-position terms, 9 clip (x, y, w) terms, 3 albedo terms
+
+template <int T>
+struct TileShape {
+    static constexpr int NPIX = T * T;
+    static constexpr int NT = NPIX < 256 ? NPIX : 256;
+    static constexpr int PPT = NPIX / NT;
+    static constexpr int NW = NT / 64;
+};
+
+// Per-workgroup sum of N per-thread values, written to dst[0..N) by threads < N.  Uniform call.
+template <int NW, int N>
+__device__ __forceinline__ void block_sum_store(const float (&val)[N], float *dst) {
+    __shared__ float part[NW][32];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    float mine = 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const float s = wave_sum(val[i]);
+        if (lane == i) mine = s;
+    }
+    if (lane < N) part[w][lane] = mine;
+    __syncthreads();
+    if (threadIdx.x < N) {
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) t += part[q][threadIdx.x];
+        dst[threadIdx.x] = t;
+    }
+}
+
+// For every triangle binned to tile gt: sum of val over the tile's pixels it
+// owns -> pair_sums[pair index][0..N), zeros when it owns none.  Marks the
+// pixels whose triangle was found.  Uniform call.
+template <int T, int N>
+__device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, int tx, int ty,
+                                               const TriSetup *__restrict__ setup,
+                                               const unsigned *__restrict__ tile_start,
+                                               const unsigned *__restrict__ bins, const unsigned *__restrict__ pair_off,
+                                               const int (&key)[TileShape<T>::PPT],
+                                               const float (&val)[TileShape<T>::PPT][N],
+                                               bool (&matched)[TileShape<T>::PPT], float *__restrict__ pair_sums) {
+    using TS = TileShape<T>;
+    __shared__ float part[TS::NW][64][N];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned b0 = tile_start[gt], b1 = tile_start[gt + 1];
+    for (unsigned c0 = b0; c0 < b1; c0 += 64) {
+        const int n = (int)min(64u, b1 - c0);
+        for (int e = 0; e < n; ++e) {
+            const int tl = (int)(bins[c0 + e] - (unsigned)v.setup_off);
+            float acc[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc[i] = 0.f;
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < TS::PPT; ++k)
+                if (key[k] == tl) {
+                    any = true;
+                    matched[k] = true;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) acc[i] += val[k][i];
+                }
+            float mine = 0.f;
+            if (__ballot(any)) {
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const float s = wave_sum(acc[i]);
+                    if (lane == i) mine = s;
+                }
+            }
+            if (lane < N) part[w][e][lane] = mine;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += TS::NT) {
+            const unsigned si = bins[c0 + e];
+            const TriSetup &st = setup[si];
+            const int tx0 = st.bx0 / T, ty0 = st.by0 / T, ntx = st.bx1 / T - tx0 + 1;
+            const unsigned p = pair_off[si] + (unsigned)((ty - ty0) * ntx + (tx - tx0));
+            float *dst = pair_sums + (size_t)p * kNV;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                float t = 0.f;
+#pragma unroll
+                for (int q = 0; q < TS::NW; ++q) t += part[q][e][i];
+                dst[i] = t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Pixels of triangles that overflowed the bins: straight to their rows of gtri.  Uniform call.
+template <int PPT, int N>
+__device__ __forceinline__ void overflow_rows(const ViewConst &v, const int (&key)[PPT], const float (&val)[PPT][N],
+                                              const bool (&active)[PPT], const bool (&matched)[PPT],
+                                              float *__restrict__ gtri) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const bool a = active[k] && !matched[k];
+        if (__ballot(a))
+            scatter_by_key(a, key[k], val[k], [&](int t, int i) { return gtri + (size_t)(v.setup_off + t) * kNV + i; });
+    }
+}
+
 // ----------------------------------------------------------------------------- lookup^T
 
-__global__ __launch_bounds__(256) void lookup_backward_kernel(
-    const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
-    const int *__restrict__ render_lights, const int *__restrict__ faces, const float *__restrict__ verts,
-    const float *__restrict__ albedo, const float4 *__restrict__ clip, const unsigned long long *__restrict__ keys,
-    const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
-    float *__restrict__ gverts, float4 *__restrict__ gclip, float *__restrict__ glight, float *__restrict__ galbedo,
-    int C) {
-    const RenderConst &R = renders[blockIdx.y];
-    const ViewConst &cv = views[R.camera_view];
-    const int W = cv.W, H = cv.H;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool inimg = p < W * H;
-    const unsigned long long key = inimg ? keys[cv.pix_off + p] : kBgKey;
-    float g[3] = {0.f, 0.f, 0.f};
-    if (inimg)
-        for (int c = 0; c < C; ++c) g[c] = gimg0[R.img_off + (long long)p * C + c];
-    bool active = key != kBgKey && (g[0] != 0.f || g[1] != 0.f || g[2] != 0.f);
-    const int tri = active ? (int)(unsigned)key : 0;
+// Gradient contributions of one camera pixel: vertex terms (gv[9] for the
+// 3 corners' world positions, gc[9] for their clip (x, y, w)), albedo terms,
+// and per-light frame terms added into accl.
+template <int MAXL>
+__device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const RenderConst &R,
+                                                  const ViewConst *__restrict__ views,
+                                                  const int *__restrict__ render_lights, const int *__restrict__ faces,
+                                                  const float *__restrict__ verts, const float *__restrict__ albedo,
+                                                  const float4 *__restrict__ clip, const float *__restrict__ maps,
+                                                  float *__restrict__ gmaps, int i, int j, int tri, const float g[3],
+                                                  int C, float (&vals)[21], float (&accl)[MAXL][22]) {
     const int *f = faces + 3 * (size_t)(cv.face_off + tri);
-    const int i = inimg ? p % W : 0, j = inimg ? p / W : 0;
-    const float px = ndc_c(i, W), py = -ndc_c(j, H);
-    float4 c0 = make_float4(0, 0, 0, 1), c1 = c0, c2 = c0;
-    float v0[3] = {0, 0, 0}, v1[3] = {0, 0, 0}, v2[3] = {0, 0, 0};
-    if (active) {
-        c0 = clip[cv.clip_off + f[0]]; c1 = clip[cv.clip_off + f[1]]; c2 = clip[cv.clip_off + f[2]];
-        for (int k = 0; k < 3; ++k) {
-            v0[k] = verts[3 * (size_t)(cv.vert_off + f[0]) + k];
-            v1[k] = verts[3 * (size_t)(cv.vert_off + f[1]) + k];
-            v2[k] = verts[3 * (size_t)(cv.vert_off + f[2]) + k];
-        }
-    } else {
-        c0 = make_float4(1, 0, 0, 1); c1 = make_float4(0, 1, 0, 1); c2 = make_float4(0, 0, 0, 1);
-        v1[0] = 1.f; v2[1] = 1.f;
+    const float px = ndc_c(i, cv.W), py = -ndc_c(j, cv.H);
+    const float4 c0 = clip[cv.clip_off + f[0]], c1 = clip[cv.clip_off + f[1]], c2 = clip[cv.clip_off + f[2]];
+    float v0[3], v1[3], v2[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v0[k] = verts[3 * (size_t)(cv.vert_off + f[0]) + k];
+        v1[k] = verts[3 * (size_t)(cv.vert_off + f[1]) + k];
+        v2[k] = verts[3 * (size_t)(cv.vert_off + f[2]) + k];
     }
     const BaryFull b = bary_full(c0, c1, c2, px, py);
     const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
@@ -193,15 +298,15 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     const float nn = sqrtf((crx * crx + cry * cry) + crz * crz);
     const float nx = crx / nn, ny = cry / nn, nz = crz / nn;
     float rho[3] = {0.f, 0.f, 0.f};
-    if (active)
-        for (int c = 0; c < C; ++c) rho[c] = albedo[(size_t)(cv.face_off + tri) * C + c];
+    for (int c = 0; c < C; ++c) rho[c] = albedo[(size_t)(cv.face_off + tri) * C + c];
     float srho = 0.f;
     for (int c = 0; c < C; ++c) srho += g[c] * rho[c];
     float gx[3] = {0, 0, 0}, gn[3] = {0, 0, 0};
     float shade = 0.f;
-    for (int q = 0; q < R.light_count; ++q) {
-        const int lidx = render_lights[R.light_begin + q];
-        const ViewConst &l = views[lidx];
+#pragma unroll
+    for (int q = 0; q < MAXL; ++q) {
+        if (q >= R.light_count) break;
+        const ViewConst &l = views[render_lights[R.light_begin + q]];
         const float *M = l.M;
         const float cx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
         const float cy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
@@ -209,7 +314,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
         const float ux = cx / cw, uy = cy / cw;
         const bool inside = cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f;
         float vis = 1.f, zz = 0.f, m1 = 0.f, m2 = 0.f, var = 0.f, dd = 0.f, fx = 0.f, fy = 0.f;
-        int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+        long long o00 = 0, o01 = 0, o10 = 0, o11 = 0;
         const int S = l.W;
         const float *ma = maps + l.map_off, *mb = maps + l.map_off + (long long)S * S;
         if (inside) {
@@ -219,11 +324,11 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             fx = sx - fx0;
             fy = sy - fy0;
             const int ix = (int)fx0, iy = (int)fy0;
-            x0 = min(max(ix, 0), S - 1); x1 = min(max(ix + 1, 0), S - 1);
-            y0 = min(max(iy, 0), S - 1); y1 = min(max(iy + 1, 0), S - 1);
+            const int x0 = min(max(ix, 0), S - 1), x1 = min(max(ix + 1, 0), S - 1);
+            const int y0 = min(max(iy, 0), S - 1), y1 = min(max(iy + 1, 0), S - 1);
             const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
-            const long long o00 = (long long)y0 * S + x0, o01 = (long long)y0 * S + x1;
-            const long long o10 = (long long)y1 * S + x0, o11 = (long long)y1 * S + x1;
+            o00 = (long long)y0 * S + x0; o01 = (long long)y0 * S + x1;
+            o10 = (long long)y1 * S + x0; o11 = (long long)y1 * S + x1;
             m1 = ((w00 * ma[o00] + w01 * ma[o01]) + w10 * ma[o10]) + w11 * ma[o11];
             m2 = ((w00 * mb[o00] + w01 * mb[o01]) + w10 * mb[o10]) + w11 * mb[o11];
             float depth;
@@ -254,13 +359,12 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             cone = ca >= l.cos_half ? 1.f : 0.f;
         }
         shade += lam * vis * l.intensity * cone;
-        const float gvis = active ? srho * lam * l.intensity * cone : 0.f;
-        const float glam = active ? srho * vis * l.intensity * cone : 0.f;
+        const float gvis = srho * lam * l.intensity * cone;
+        const float glam = srho * vis * l.intensity * cone;
         const float gndo = ndo > 0.f ? glam : 0.f;
         gn[0] += gndo * ox; gn[1] += gndo * oy; gn[2] += gndo * oz;
         const float gox = gndo * nx, goy = gndo * ny, goz = gndo * nz;
-        float gl[22];
-        for (int k = 0; k < 22; ++k) gl[k] = 0.f;   // M[16], pos[3], dir[3]
+        float *gl = accl[q];   // M[16], pos[3], dir[3]
         if (l.kind == kDirectional) {
             gl[19] -= gox; gl[20] -= goy; gl[21] -= goz;
         } else {
@@ -276,8 +380,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             const float dv_dvar = clamped ? 0.f : dd * dd / (qd * qd);
             const float gm1 = gvis * (dv_dmu - 2.f * m1 * dv_dvar);
             const float gm2 = gvis * dv_dvar;
-            const float gz = -gvis * dv_dmu;
-            const float gdepth = gz / l.zfar;
+            const float gdepth = -gvis * dv_dmu / l.zfar;
             if (l.kind == kDirectional) {
                 gx[0] += gdepth * l.dir[0]; gx[1] += gdepth * l.dir[1]; gx[2] += gdepth * l.dir[2];
                 gl[16] -= gdepth * l.dir[0]; gl[17] -= gdepth * l.dir[1]; gl[18] -= gdepth * l.dir[2];
@@ -292,13 +395,11 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             // bilinear scatter to the moment maps
             float *ga = gmaps + l.map_off, *gb = gmaps + l.map_off + (long long)S * S;
             const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
-            const long long o00 = (long long)y0 * S + x0, o01 = (long long)y0 * S + x1;
-            const long long o10 = (long long)y1 * S + x0, o11 = (long long)y1 * S + x1;
             atomic_add_f32(ga + o00, gm1 * w00); atomic_add_f32(ga + o01, gm1 * w01);
             atomic_add_f32(ga + o10, gm1 * w10); atomic_add_f32(ga + o11, gm1 * w11);
             atomic_add_f32(gb + o00, gm2 * w00); atomic_add_f32(gb + o01, gm2 * w01);
             atomic_add_f32(gb + o10, gm2 * w10); atomic_add_f32(gb + o11, gm2 * w11);
-            // position in the map moves with x and with the light camera
+            // the map position moves with x and with the light camera
             const float dm1fx = (1.f - fy) * (ma[o01] - ma[o00]) + fy * (ma[o11] - ma[o10]);
             const float dm1fy = (1.f - fx) * (ma[o10] - ma[o00]) + fx * (ma[o11] - ma[o01]);
             const float dm2fx = (1.f - fy) * (mb[o01] - mb[o00]) + fy * (mb[o11] - mb[o10]);
@@ -309,6 +410,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             const float gcx = gsx * hs / cw, gcy = -gsy * hs / cw;
             const float gcw = (-gsx * hs * cx + gsy * hs * cy) / (cw * cw);
             const float xh[4] = {x, y, z, 1.f};
+#pragma unroll
             for (int k = 0; k < 4; ++k) {
                 gl[k] += gcx * xh[k];
                 gl[4 + k] += gcy * xh[k];
@@ -316,193 +418,380 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             }
             for (int k = 0; k < 3; ++k) gx[k] += (M[k] * gcx + M[4 + k] * gcy) + M[12 + k] * gcw;
         }
-        wave_add(gl, glight + 24 * lidx);
     }
     // albedo
-    float ga3[3];
-    for (int c = 0; c < 3; ++c) ga3[c] = c < C ? g[c] * shade : 0.f;
-    scatter_by_key(active, tri, ga3, [&](int k, int c) { return galbedo + (size_t)(cv.face_off + k) * C + (c < C ? c : 0); });
+    for (int c = 0; c < 3; ++c) vals[18 + c] = c < C ? g[c] * shade : 0.f;
     // normal: n = cr / |cr|, cr = e1 x e2
     const float ndg = (nx * gn[0] + ny * gn[1]) + nz * gn[2];
     const float gcr[3] = {(gn[0] - nx * ndg) / nn, (gn[1] - ny * ndg) / nn, (gn[2] - nz * ndg) / nn};
     const float ge1[3] = {e2y * gcr[2] - e2z * gcr[1], e2z * gcr[0] - e2x * gcr[2], e2x * gcr[1] - e2y * gcr[0]};
     const float ge2[3] = {gcr[1] * e1z - gcr[2] * e1y, gcr[2] * e1x - gcr[0] * e1z, gcr[0] * e1y - gcr[1] * e1x};
     // x = sum b_i v_i
-    float gv[9];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        gv[k] = b.b0 * gx[k] - ge1[k] - ge2[k];
-        gv[3 + k] = b.b1 * gx[k] + ge1[k];
-        gv[6 + k] = b.b2 * gx[k] + ge2[k];
+        vals[k] = b.b0 * gx[k] - ge1[k] - ge2[k];
+        vals[3 + k] = b.b1 * gx[k] + ge1[k];
+        vals[6 + k] = b.b2 * gx[k] + ge2[k];
     }
     const float gb0 = (gx[0] * v0[0] + gx[1] * v0[1]) + gx[2] * v0[2];
     const float gb1 = (gx[0] * v1[0] + gx[1] * v1[1]) + gx[2] * v1[2];
     const float gb2 = (gx[0] * v2[0] + gx[1] * v2[1]) + gx[2] * v2[2];
     float gc[9];
     bary_backward(b, px, py, gb0, gb1, gb2, gc);
-    const int vo = cv.vert_off, co = cv.clip_off, fo = cv.face_off;
-    scatter_by_key(active, tri, gv, [&](int k, int e) {
-        return gverts + 3 * (size_t)(vo + faces[3 * (size_t)(fo + k) + e / 3]) + (e % 3);
-    });
-    scatter_by_key(active, tri, gc, [&](int k, int e) {
-        float4 *t = gclip + co + faces[3 * (size_t)(fo + k) + e / 3];
-        const int comp = e % 3;
-        return comp == 0 ? &t->x : (comp == 1 ? &t->y : &t->w);
-    });
+#pragma unroll
+    for (int k = 0; k < 9; ++k) vals[9 + k] = gc[k];
+}
+
+template <int T, int MAXL>
+__global__ __launch_bounds__(256) void lookup_backward_kernel(
+    const ViewConst *__restrict__ views, int L, const RenderConst *__restrict__ renders,
+    const int *__restrict__ cam_renders_off, const int *__restrict__ cam_renders,
+    const int *__restrict__ render_lights, const int *__restrict__ faces, const float *__restrict__ verts,
+    const float *__restrict__ albedo, const float4 *__restrict__ clip, const unsigned long long *__restrict__ keys,
+    const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
+    const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
+    const unsigned *__restrict__ pair_off, float *__restrict__ pair_sums, float *__restrict__ gtri,
+    float *__restrict__ part_render, int C) {
+    using TS = TileShape<T>;
+    const int cam = blockIdx.y;
+    const ViewConst &cv = views[L + cam];
+    const int lt = blockIdx.x;
+    if (lt >= cv.tiles_x * cv.tiles_y) return;     // whole workgroup
+    const int gt = cv.tile_off + lt;
+    const int tx = lt % cv.tiles_x, ty = lt / cv.tiles_x;
+    const int tid = threadIdx.x;
+    int key[TS::PPT], pi[TS::PPT], pj[TS::PPT];
+    bool act[TS::PPT], matched[TS::PPT];
+    float val[TS::PPT][kNV];
+#pragma unroll
+    for (int k = 0; k < TS::PPT; ++k) {
+        const int l = tid + k * TS::NT;
+        pi[k] = tx * T + (l % T);
+        pj[k] = ty * T + (l / T);
+        const bool in = pi[k] < cv.W && pj[k] < cv.H;
+        const unsigned long long kk = in ? keys[cv.pix_off + (long long)pj[k] * cv.W + pi[k]] : kBgKey;
+        key[k] = kk == kBgKey ? -1 : (int)(unsigned)kk;
+        act[k] = false;
+        matched[k] = false;
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) val[k][i] = 0.f;
+    }
+    for (int rr = cam_renders_off[cam]; rr < cam_renders_off[cam + 1]; ++rr) {
+        const int r = cam_renders[rr];
+        const RenderConst &R = renders[r];
+        float accl[MAXL][22];
+#pragma unroll
+        for (int q = 0; q < MAXL; ++q)
+#pragma unroll
+            for (int i = 0; i < 22; ++i) accl[q][i] = 0.f;
+#pragma unroll
+        for (int k = 0; k < TS::PPT; ++k) {
+            if (key[k] < 0) continue;
+            const long long p = (long long)pj[k] * cv.W + pi[k];
+            float g[3] = {0.f, 0.f, 0.f};
+            for (int c = 0; c < C; ++c) g[c] = gimg0[R.img_off + p * C + c];
+            if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) continue;
+            float tmp[kNV];
+            lookup_pixel_grad<MAXL>(cv, R, views, render_lights, faces, verts, albedo, clip, maps, gmaps, pi[k], pj[k],
+                                    key[k], g, C, tmp, accl);
+            act[k] = true;
+#pragma unroll
+            for (int i = 0; i < kNV; ++i) val[k][i] += tmp[i];
+        }
+        const int ntiles = cv.tiles_x * cv.tiles_y;
+#pragma unroll
+        for (int q = 0; q < MAXL; ++q) {
+            if (q >= R.light_count) break;
+            block_sum_store<TS::NW>(accl[q], part_render + R.part_off + ((long long)q * ntiles + lt) * 22);
+        }
+    }
+    tile_pair_sums<T, kNV>(cv, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, matched, pair_sums);
+    overflow_rows(cv, key, val, act, matched, gtri);
 }
 
 // ----------------------------------------------------------------------------- light smoothing^T + resolve^T
 
+template <int T>
 __global__ __launch_bounds__(256) void light_backward_kernel(
     const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup, const int *__restrict__ faces,
     const int *__restrict__ adj, const float *__restrict__ verts, const float4 *__restrict__ clip,
     const unsigned long long *__restrict__ keys, const float *__restrict__ F0, const float *__restrict__ gF1,
-    float *__restrict__ gverts, float4 *__restrict__ gclip, float *__restrict__ glight) {
+    float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
+    const unsigned *__restrict__ pair_off, float *__restrict__ pair_sums, float *__restrict__ gtri,
+    float *__restrict__ part_light) {
+    using TS = TileShape<T>;
     const int lidx = blockIdx.y;
     const ViewConst &l = views[lidx];
     const int S = l.W;
     const long long plane = (long long)S * S;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = p < S * S;
-    const int pp = in ? p : 0;
-    const int i = pp % S, j = pp / S;
+    const int lt = blockIdx.x;
+    if (lt >= l.tiles_x * l.tiles_y) return;     // whole workgroup
+    const int gt = l.tile_off + lt;
+    const int tx = lt % l.tiles_x, ty = lt / l.tiles_x;
     const unsigned long long *kv = keys + l.pix_off;
-    const unsigned long long ks = kv[pp];
     const float *f0a = F0 + l.map_off, *f0b = F0 + l.map_off + plane;
     const float *ga = gF1 + l.map_off, *gbp = gF1 + l.map_off + plane;
-    float g0 = in ? ga[pp] : 0.f, g1 = in ? gbp[pp] : 0.f;
-    if (in && l.antialias) {
-        const float gs0 = g0, gs1 = g1;
-        const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
-        for (int d = 0; d < 4; ++d) {
-            const int in_ = i + di[d], jn = j + dj[d];
-            if (in_ < 0 || in_ >= S || jn < 0 || jn >= S) continue;
-            const int q = jn * S + in_;
-            const unsigned long long kn = kv[q];
-            if ((unsigned)kn == (unsigned)ks) continue;
-            bool self_front;
-            AAPair pr;
-            if (!aa_eval<true>(l, setup, faces, adj, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
-            const bool self_recv = (pr.recv == 1) != self_front;
-            if (self_recv) {
-                g0 -= pr.w * gs0;
-                g1 -= pr.w * gs1;
-                double galpha = (double)gs0 * (f0a[q] - f0a[pp]) + (double)gs1 * (f0b[q] - f0b[pp]);
-                galpha *= pr.recv == 1 ? 1.0 : -1.0;
-                float4 *gpa = gclip + l.clip_off + pr.va;
-                float4 *gpb = gclip + l.clip_off + pr.vb;
-                atomic_add_f32(&gpa->x, (float)(galpha * pr.dax));
-                atomic_add_f32(&gpa->y, (float)(galpha * pr.day));
-                atomic_add_f32(&gpa->w, (float)(galpha * pr.daw));
-                atomic_add_f32(&gpb->x, (float)(galpha * pr.dbx));
-                atomic_add_f32(&gpb->y, (float)(galpha * pr.dby));
-                atomic_add_f32(&gpb->w, (float)(galpha * pr.dbw));
-            } else {
-                g0 += pr.w * ga[q];
-                g1 += pr.w * gbp[q];
+    float accl[6] = {0, 0, 0, 0, 0, 0};
+    int key[TS::PPT];
+    bool act[TS::PPT], matched[TS::PPT];
+    float val[TS::PPT][18];
+#pragma unroll
+    for (int k = 0; k < TS::PPT; ++k) {
+        const int lix = threadIdx.x + k * TS::NT;
+        const int i = tx * T + (lix % T), j = ty * T + (lix / T);
+        const bool in = i < S && j < S;
+        const int pp = in ? j * S + i : 0;
+        const unsigned long long ks = kv[pp];
+        key[k] = (in && ks != kBgKey) ? (int)(unsigned)ks : -1;
+        matched[k] = false;
+#pragma unroll
+        for (int q = 0; q < 18; ++q) val[k][q] = 0.f;
+        float g0 = in ? ga[pp] : 0.f, g1 = in ? gbp[pp] : 0.f;
+        if (in && l.antialias) {
+            const float gs0 = g0, gs1 = g1;
+            const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+            for (int d = 0; d < 4; ++d) {
+                const int in_ = i + di[d], jn = j + dj[d];
+                if (in_ < 0 || in_ >= S || jn < 0 || jn >= S) continue;
+                const int q = jn * S + in_;
+                const unsigned long long kn = kv[q];
+                if ((unsigned)kn == (unsigned)ks) continue;
+                bool self_front;
+                AAPair pr;
+                if (!aa_eval<true>(l, setup, faces, adj, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
+                const bool self_recv = (pr.recv == 1) != self_front;
+                if (self_recv) {
+                    g0 -= pr.w * gs0;
+                    g1 -= pr.w * gs1;
+                    double galpha = (double)gs0 * (f0a[q] - f0a[pp]) + (double)gs1 * (f0b[q] - f0b[pp]);
+                    galpha *= pr.recv == 1 ? 1.0 : -1.0;
+                    float4 *gpa = gclip + l.clip_off + pr.va;
+                    float4 *gpb = gclip + l.clip_off + pr.vb;
+                    atomic_add_f32(&gpa->x, (float)(galpha * pr.dax));
+                    atomic_add_f32(&gpa->y, (float)(galpha * pr.day));
+                    atomic_add_f32(&gpa->w, (float)(galpha * pr.daw));
+                    atomic_add_f32(&gpb->x, (float)(galpha * pr.dbx));
+                    atomic_add_f32(&gpb->y, (float)(galpha * pr.dby));
+                    atomic_add_f32(&gpb->w, (float)(galpha * pr.dbw));
+                } else {
+                    g0 += pr.w * ga[q];
+                    g1 += pr.w * gbp[q];
+                }
             }
         }
-    }
-    // resolve^T: F0 = (z, z^2), z = d(x) / far
-    const bool active = in && ks != kBgKey && (g0 != 0.f || g1 != 0.f);
-    const int tri = active ? (int)(unsigned)ks : 0;
-    const int *f = faces + 3 * (size_t)(l.face_off + tri);
-    float4 c0 = make_float4(1, 0, 0, 1), c1 = make_float4(0, 1, 0, 1), c2 = make_float4(0, 0, 0, 1);
-    float v0[3] = {0, 0, 0}, v1[3] = {1, 0, 0}, v2[3] = {0, 1, 0};
-    if (active) {
-        c0 = clip[l.clip_off + f[0]]; c1 = clip[l.clip_off + f[1]]; c2 = clip[l.clip_off + f[2]];
-        for (int k = 0; k < 3; ++k) {
-            v0[k] = verts[3 * (size_t)(l.vert_off + f[0]) + k];
-            v1[k] = verts[3 * (size_t)(l.vert_off + f[1]) + k];
-            v2[k] = verts[3 * (size_t)(l.vert_off + f[2]) + k];
+        // resolve^T: F0 = (z, z^2), z = d(x) / far
+        act[k] = key[k] >= 0 && (g0 != 0.f || g1 != 0.f);
+        if (act[k]) {
+            const int *f = faces + 3 * (size_t)(l.face_off + key[k]);
+            const float4 c0 = clip[l.clip_off + f[0]], c1 = clip[l.clip_off + f[1]], c2 = clip[l.clip_off + f[2]];
+            float v0[3], v1[3], v2[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                v0[q] = verts[3 * (size_t)(l.vert_off + f[0]) + q];
+                v1[q] = verts[3 * (size_t)(l.vert_off + f[1]) + q];
+                v2[q] = verts[3 * (size_t)(l.vert_off + f[2]) + q];
+            }
+            const float px = ndc_c(i, S), py = -ndc_c(j, S);
+            const BaryFull b = bary_full(c0, c1, c2, px, py);
+            const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
+            const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
+            const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
+            const float gz = g0 + 2.f * f0a[pp] * g1;
+            const float gdepth = gz / l.zfar;
+            float gx[3];
+            if (l.kind == kDirectional) {
+                gx[0] = gdepth * l.dir[0]; gx[1] = gdepth * l.dir[1]; gx[2] = gdepth * l.dir[2];
+                accl[0] -= gx[0]; accl[1] -= gx[1]; accl[2] -= gx[2];
+                accl[3] += gdepth * (x - l.pos[0]); accl[4] += gdepth * (y - l.pos[1]); accl[5] += gdepth * (z - l.pos[2]);
+            } else {
+                const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
+                const float dl = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
+                const float inv = gdepth / dl;
+                gx[0] = ddx * inv; gx[1] = ddy * inv; gx[2] = ddz * inv;
+                accl[0] -= gx[0]; accl[1] -= gx[1]; accl[2] -= gx[2];
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                val[k][q] = b.b0 * gx[q];
+                val[k][3 + q] = b.b1 * gx[q];
+                val[k][6 + q] = b.b2 * gx[q];
+            }
+            const float gb0 = (gx[0] * v0[0] + gx[1] * v0[1]) + gx[2] * v0[2];
+            const float gb1 = (gx[0] * v1[0] + gx[1] * v1[1]) + gx[2] * v1[2];
+            const float gb2 = (gx[0] * v2[0] + gx[1] * v2[1]) + gx[2] * v2[2];
+            float gc[9];
+            bary_backward(b, px, py, gb0, gb1, gb2, gc);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) val[k][9 + q] = gc[q];
         }
     }
-    const float px = ndc_c(i, S), py = -ndc_c(j, S);
-    const BaryFull b = bary_full(c0, c1, c2, px, py);
-    const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
-    const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
-    const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
-    const float zval = active ? f0a[pp] : 0.f;
-    const float gz = active ? g0 + 2.f * zval * g1 : 0.f;
-    const float gdepth = gz / l.zfar;
-    float gx[3], gl[6];
-    if (l.kind == kDirectional) {
-        gx[0] = gdepth * l.dir[0]; gx[1] = gdepth * l.dir[1]; gx[2] = gdepth * l.dir[2];
-        gl[0] = -gx[0]; gl[1] = -gx[1]; gl[2] = -gx[2];
-        gl[3] = gdepth * (x - l.pos[0]); gl[4] = gdepth * (y - l.pos[1]); gl[5] = gdepth * (z - l.pos[2]);
-    } else {
-        const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
-        const float dl = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
-        const float inv = active ? gdepth / dl : 0.f;
-        gx[0] = ddx * inv; gx[1] = ddy * inv; gx[2] = ddz * inv;
-        gl[0] = -gx[0]; gl[1] = -gx[1]; gl[2] = -gx[2];
-        gl[3] = gl[4] = gl[5] = 0.f;
-    }
-    wave_add(gl, glight + 24 * lidx + 16);
-    float gv[9];
-    for (int k = 0; k < 3; ++k) {
-        gv[k] = b.b0 * gx[k];
-        gv[3 + k] = b.b1 * gx[k];
-        gv[6 + k] = b.b2 * gx[k];
-    }
-    const float gb0 = (gx[0] * v0[0] + gx[1] * v0[1]) + gx[2] * v0[2];
-    const float gb1 = (gx[0] * v1[0] + gx[1] * v1[1]) + gx[2] * v1[2];
-    const float gb2 = (gx[0] * v2[0] + gx[1] * v2[1]) + gx[2] * v2[2];
-    float gc[9];
-    bary_backward(b, px, py, gb0, gb1, gb2, gc);
-    const int vo = l.vert_off, co = l.clip_off, fo = l.face_off;
-    scatter_by_key(active, tri, gv, [&](int k, int e) {
-        return gverts + 3 * (size_t)(vo + faces[3 * (size_t)(fo + k) + e / 3]) + (e % 3);
-    });
-    scatter_by_key(active, tri, gc, [&](int k, int e) {
-        float4 *t = gclip + co + faces[3 * (size_t)(fo + k) + e / 3];
-        const int comp = e % 3;
-        return comp == 0 ? &t->x : (comp == 1 ? &t->y : &t->w);
-    });
+    block_sum_store<TS::NW>(accl, part_light + ((long long)l.part_off + lt) * 6);
+    tile_pair_sums<T, 18>(l, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, matched, pair_sums);
+    overflow_rows(l, key, val, act, matched, gtri);
 }
 
-// ----------------------------------------------------------------------------- transform^T
+// ----------------------------------------------------------------------------- gathers
 
-__global__ __launch_bounds__(256) void transform_backward_kernel(const ViewConst *__restrict__ views, int L,
-                                                                 const float *__restrict__ verts,
-                                                                 const float4 *__restrict__ gclip,
-                                                                 float *__restrict__ gverts,
-                                                                 float *__restrict__ glight) {
-    const int view = blockIdx.y;
-    const ViewConst &v = views[view];
+// Zero the gtri rows of triangles that overflowed the bins (their pixels are
+// added there with atomics) and reset the big-triangle list.
+__global__ void overflow_rows_zero_kernel(const unsigned *__restrict__ list, const DevCounters *counters,
+                                          float *__restrict__ gtri) {
+    const unsigned n = counters->overflow_list_len;
+    for (unsigned o = blockIdx.x; o < n; o += gridDim.x)
+        for (int i = threadIdx.x; i < kNV; i += blockDim.x) gtri[(size_t)list[o] * kNV + i] = 0.f;
+}
+
+constexpr unsigned kBigPairs = 16;
+
+// gtri[i] = sum of triangle i's pair slots (triangles with many pairs are listed for the big pass).
+__global__ void pair_reduce_kernel(const unsigned *__restrict__ pair_off, int ntri, unsigned capacity,
+                                   const float *__restrict__ pair_sums, float *__restrict__ gtri,
+                                   unsigned *__restrict__ big_list, unsigned *__restrict__ big_count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = i < v.nverts;
-    const float4 g = in ? gclip[v.clip_off + i] : make_float4(0, 0, 0, 0);
-    const float *M = v.M;
-    if (in && (g.x != 0.f || g.y != 0.f || g.w != 0.f)) {
-        float *dst = gverts + 3 * (size_t)(v.vert_off + i);
-        for (int k = 0; k < 3; ++k) atomic_add_f32(dst + k, (M[k] * g.x + M[4 + k] * g.y) + M[12 + k] * g.w);
+    if (i >= ntri) return;
+    const unsigned a = pair_off[i], b = pair_off[i + 1];
+    if (b > capacity && b > a) return;            // overflowed: rows filled by atomics
+    if (b - a > kBigPairs) {
+        big_list[atomicAdd(big_count, 1u)] = (unsigned)i;
+        return;
     }
-    if (view < L) {
-        float xh[4] = {0, 0, 0, 0};
-        if (in) {
-            const float *p = verts + 3 * (size_t)(v.vert_off + i);
-            xh[0] = p[0]; xh[1] = p[1]; xh[2] = p[2]; xh[3] = 1.f;
-        }
-        float gm[16];
-        for (int k = 0; k < 4; ++k) {
-            gm[k] = g.x * xh[k];
-            gm[4 + k] = g.y * xh[k];
-            gm[8 + k] = 0.f;
-            gm[12 + k] = g.w * xh[k];
-        }
-        // one atomic set per workgroup: wave sums then LDS
-        __shared__ float part[4][16];
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-        for (int k = 0; k < 16; ++k) {
-            const float s = wave_sum(gm[k]);
-            if (lane == 0) part[wid][k] = s;
-        }
+    float acc[kNV];
+#pragma unroll
+    for (int q = 0; q < kNV; ++q) acc[q] = 0.f;
+    for (unsigned p = a; p < b; ++p)
+#pragma unroll
+        for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
+#pragma unroll
+    for (int q = 0; q < kNV; ++q) gtri[(size_t)i * kNV + q] = acc[q];
+}
+
+__global__ __launch_bounds__(256) void big_pair_reduce_kernel(const unsigned *__restrict__ pair_off,
+                                                              const float *__restrict__ pair_sums,
+                                                              float *__restrict__ gtri,
+                                                              const unsigned *__restrict__ big_list,
+                                                              const unsigned *__restrict__ big_count) {
+    const unsigned n = *big_count;
+    for (unsigned o = blockIdx.x; o < n; o += gridDim.x) {
+        const unsigned i = big_list[o];
+        const unsigned a = pair_off[i], b = pair_off[i + 1];
+        float acc[kNV];
+#pragma unroll
+        for (int q = 0; q < kNV; ++q) acc[q] = 0.f;
+        for (unsigned p = a + threadIdx.x; p < b; p += blockDim.x)
+#pragma unroll
+            for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
+        block_sum_store<4>(acc, gtri + (size_t)i * kNV);
         __syncthreads();
-        if (threadIdx.x < 16) {
-            const float s = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
-            atomic_add_f32(glight + 24 * view + threadIdx.x, s);
+    }
+}
+
+// Per vertex: sum its triangle corners' terms over every view of its scene,
+// add the silhouette clip terms, map clip terms through M^T; per light view
+// the workgroup's share of dL/dM is written for glight_reduce.
+__global__ __launch_bounds__(256) void vertex_gather_kernel(
+    const ViewConst *__restrict__ views, int L, const int *__restrict__ scene_vert_off,
+    const int *__restrict__ scene_views_off, const int *__restrict__ scene_views, const int *__restrict__ vc_off,
+    const int *__restrict__ vc_list, const float *__restrict__ verts, const float *__restrict__ gtri,
+    const float4 *__restrict__ gclip, float *__restrict__ gverts, float *__restrict__ part_gm) {
+    const int b = blockIdx.y;
+    const int nv = scene_vert_off[b + 1] - scene_vert_off[b];
+    if ((int)(blockIdx.x * blockDim.x) >= nv) return;        // whole workgroup
+    const int vl = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = vl < nv;
+    const int gv_idx = scene_vert_off[b] + (in ? vl : 0);
+    float x[3] = {0, 0, 0};
+    if (in)
+        for (int k = 0; k < 3; ++k) x[k] = verts[3 * (size_t)gv_idx + k];
+    float gv[3] = {0, 0, 0};
+    const int c0 = in ? vc_off[gv_idx] : 0, c1 = in ? vc_off[gv_idx + 1] : 0;
+    for (int s = scene_views_off[b]; s < scene_views_off[b + 1]; ++s) {
+        const int vi = scene_views[s];
+        const ViewConst &v = views[vi];
+        float gc[3] = {0, 0, 0};
+        for (int c = c0; c < c1; ++c) {
+            const int e = vc_list[c];
+            const float *row = gtri + (size_t)(v.setup_off + (e >> 2)) * kNV;
+            const int corner = e & 3;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                gv[k] += row[corner * 3 + k];
+                gc[k] += row[9 + corner * 3 + k];
+            }
+        }
+        if (in) {
+            const float4 ga = gclip[v.clip_off + vl];
+            gc[0] += ga.x; gc[1] += ga.y; gc[2] += ga.w;
+        }
+        const float *M = v.M;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gv[k] += (M[k] * gc[0] + M[4 + k] * gc[1]) + M[12 + k] * gc[2];
+        if (vi < L) {
+            const float xh[4] = {x[0], x[1], x[2], in ? 1.f : 0.f};
+            float gm[16];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                gm[k] = gc[0] * xh[k];
+                gm[4 + k] = gc[1] * xh[k];
+                gm[8 + k] = 0.f;
+                gm[12 + k] = gc[2] * xh[k];
+            }
+            block_sum_store<4>(gm, part_gm + ((long long)v.part_gm_off + blockIdx.x) * 16);
         }
     }
+    if (in)
+        for (int k = 0; k < 3; ++k) gverts[3 * (size_t)gv_idx + k] = gv[k];
+}
+
+// Albedo gradient per face: sum over the camera views of its scene.
+__global__ void albedo_gather_kernel(const ViewConst *__restrict__ views, int L, const int *__restrict__ scene_face_off,
+                                     const int *__restrict__ scene_views_off, const int *__restrict__ scene_views,
+                                     const float *__restrict__ gtri, float *__restrict__ galbedo, int C) {
+    const int b = blockIdx.y;
+    const int fl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fl >= scene_face_off[b + 1] - scene_face_off[b]) return;
+    float acc[3] = {0, 0, 0};
+    for (int s = scene_views_off[b]; s < scene_views_off[b + 1]; ++s) {
+        const int vi = scene_views[s];
+        if (vi < L) continue;
+        const float *row = gtri + (size_t)(views[vi].setup_off + fl) * kNV;
+        for (int c = 0; c < C; ++c) acc[c] += row[18 + c];
+    }
+    for (int c = 0; c < C; ++c) galbedo[(size_t)(scene_face_off[b] + fl) * C + c] = acc[c];
+}
+
+// glight[l] = sum of every partial written for light l (vertex blocks, light
+// tiles, and the tiles of each render that uses it).
+__global__ __launch_bounds__(256) void glight_reduce_kernel(const ViewConst *__restrict__ views,
+                                                            const RenderConst *__restrict__ renders,
+                                                            const int *__restrict__ light_renders_off,
+                                                            const int *__restrict__ light_renders,
+                                                            const float *__restrict__ part_gm,
+                                                            const float *__restrict__ part_light,
+                                                            const float *__restrict__ part_render,
+                                                            float *__restrict__ glight) {
+    const int l = blockIdx.x;
+    const ViewConst &v = views[l];
+    float acc[22];
+#pragma unroll
+    for (int k = 0; k < 22; ++k) acc[k] = 0.f;
+    const int nvb = (v.nverts + 255) / 256;
+    for (int q = threadIdx.x; q < nvb; q += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] += part_gm[((long long)v.part_gm_off + q) * 16 + k];
+    const int nlt = v.tiles_x * v.tiles_y;
+    for (int q = threadIdx.x; q < nlt; q += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[16 + k] += part_light[((long long)v.part_off + q) * 6 + k];
+    for (int e = light_renders_off[l]; e < light_renders_off[l + 1]; ++e) {
+        const int r = light_renders[e] >> 5, slot = light_renders[e] & 31;
+        const RenderConst &R = renders[r];
+        const ViewConst &cv = views[R.camera_view];
+        const int nct = cv.tiles_x * cv.tiles_y;
+        for (int q = threadIdx.x; q < nct; q += blockDim.x)
+#pragma unroll
+            for (int k = 0; k < 22; ++k) acc[k] += part_render[R.part_off + ((long long)slot * nct + q) * 22 + k];
+    }
+    block_sum_store<4>(acc, glight + 24 * l);
 }
 
 // ----------------------------------------------------------------------------- pose
@@ -623,33 +912,81 @@ hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *
     return hipGetLastError();
 }
 
-hipError_t launch_lookup_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
-                                  const int *render_lights, const int *faces, const float *verts,
-                                  const float *albedo, const float4 *clip, const unsigned long long *keys,
-                                  const float *maps, const float *gimg0, float *gmaps, float *gverts,
-                                  float4 *gclip, float *glight, float *galbedo, int C, hipStream_t s) {
-    if (R == 0) return hipSuccess;
-    hipLaunchKernelGGL(lookup_backward_kernel, dim3((max_pix + 255) / 256, R), dim3(256), 0, s, views, renders,
-                       render_lights, faces, verts, albedo, clip, keys, maps, gimg0, gmaps, gverts, gclip, glight,
-                       galbedo, C);
+hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int Cm, int max_tiles, int max_lights,
+                                  const RenderConst *renders, const int *cam_renders_off, const int *cam_renders,
+                                  const int *render_lights, const int *faces, const float *verts, const float *albedo,
+                                  const float4 *clip, const unsigned long long *keys, const float *maps,
+                                  const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
+                                  const unsigned *bins, const unsigned *pair_off, float *pair_sums, float *gtri,
+                                  float *part_render, int C, hipStream_t s) {
+    if (Cm == 0 || max_tiles == 0) return hipSuccess;
+    const dim3 grid(max_tiles, Cm);
+#define DSM_LB(TT, ML)                                                                                              \
+    hipLaunchKernelGGL((lookup_backward_kernel<TT, ML>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,   \
+                       cam_renders_off, cam_renders, render_lights, faces, verts, albedo, clip, keys, maps, gimg0,   \
+                       gmaps, setup, tile_start, bins, pair_off, pair_sums, gtri, part_render, C)
+#define DSM_LB_T(TT)                                                  \
+    if (max_lights <= 1) DSM_LB(TT, 1);                               \
+    else if (max_lights <= 4) DSM_LB(TT, 4);                          \
+    else DSM_LB(TT, DSM_MAX_LIGHTS_PER_RENDER)
+    if (tile == 8) { DSM_LB_T(8); }
+    else if (tile == 16) { DSM_LB_T(16); }
+    else { DSM_LB_T(32); }
+#undef DSM_LB_T
+#undef DSM_LB
     return hipGetLastError();
 }
 
-hipError_t launch_light_backward(const ViewConst *views, int L, int max_texels, const TriSetup *setup,
+hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const int *adj, const float *verts, const float4 *clip,
-                                 const unsigned long long *keys, const float *F0, const float *gF1, float *gverts,
-                                 float4 *gclip, float *glight, hipStream_t s) {
-    if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(light_backward_kernel, dim3((max_texels + 255) / 256, L), dim3(256), 0, s, views, setup,
-                       faces, adj, verts, clip, keys, F0, gF1, gverts, gclip, glight);
+                                 const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
+                                 const unsigned *tile_start, const unsigned *bins, const unsigned *pair_off,
+                                 float *pair_sums, float *gtri, float *part_light, hipStream_t s) {
+    if (L == 0 || max_tiles == 0) return hipSuccess;
+    const dim3 grid(max_tiles, L);
+#define DSM_LIB(TT)                                                                                                  \
+    hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, adj,   \
+                       verts, clip, keys, F0, gF1, gclip, tile_start, bins, pair_off, pair_sums, gtri, part_light)
+    if (tile == 8) DSM_LIB(8);
+    else if (tile == 16) DSM_LIB(16);
+    else DSM_LIB(32);
+#undef DSM_LIB
     return hipGetLastError();
 }
 
-hipError_t launch_transform_backward(const ViewConst *views, int nviews, int L, int max_verts, const float *verts,
-                                     const float4 *gclip, float *gverts, float *glight, hipStream_t s) {
-    if (nviews == 0 || max_verts == 0) return hipSuccess;
-    hipLaunchKernelGGL(transform_backward_kernel, dim3((max_verts + 255) / 256, nviews), dim3(256), 0, s, views, L,
-                       verts, gclip, gverts, glight);
+hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max_verts, int max_faces, int ntri,
+                                   unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
+                                   const int *scene_views_off, const int *scene_views, const int *vc_off,
+                                   const int *vc_list, const unsigned *pair_off, const float *pair_sums, float *gtri,
+                                   unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
+                                   float *gverts, float *part_gm, float *galbedo, int C, hipStream_t s) {
+    if (ntri > 0) {
+        hipLaunchKernelGGL(pair_reduce_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
+                           pair_sums, gtri, big_list, big_count);
+        hipLaunchKernelGGL(big_pair_reduce_kernel, dim3(512), dim3(256), 0, s, pair_off, pair_sums, gtri, big_list,
+                           (const unsigned *)big_count);
+    }
+    if (max_verts > 0)
+        hipLaunchKernelGGL(vertex_gather_kernel, dim3((max_verts + 255) / 256, B), dim3(256), 0, s, views, L,
+                           scene_vert_off, scene_views_off, scene_views, vc_off, vc_list, verts, gtri, gclip, gverts,
+                           part_gm);
+    if (galbedo && max_faces > 0)
+        hipLaunchKernelGGL(albedo_gather_kernel, dim3((max_faces + 255) / 256, B), dim3(256), 0, s, views, L,
+                           scene_face_off, scene_views_off, scene_views, gtri, galbedo, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *counters, float *gtri, hipStream_t s) {
+    hipLaunchKernelGGL(overflow_rows_zero_kernel, dim3(256), dim3(64), 0, s, list, counters, gtri);
+    return hipGetLastError();
+}
+
+hipError_t launch_glight_reduce(const ViewConst *views, int L, const RenderConst *renders,
+                                const int *light_renders_off, const int *light_renders, const float *part_gm,
+                                const float *part_light, const float *part_render, float *glight, hipStream_t s) {
+    if (L == 0) return hipSuccess;
+    hipLaunchKernelGGL(glight_reduce_kernel, dim3(L), dim3(256), 0, s, views, renders, light_renders_off,
+                       light_renders, part_gm, part_light, part_render, glight);
     return hipGetLastError();
 }
 

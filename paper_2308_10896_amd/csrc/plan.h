@@ -19,6 +19,8 @@ struct dsm_plan {
     int max_verts = 0, max_faces = 0, max_light_texels = 0, max_cam_pix = 0;
     long long key_count = 0, map_floats = 0, image_floats = 0;
     int blur_tiles = 0, blur_rmax = 0, max_pose_verts = 0;
+    int max_light_tiles = 0, max_cam_tiles = 0, max_lights_per_render = 0;
+    int max_scene_verts = 0, max_scene_faces = 0;
 
     std::vector<dsm::ViewConst> views_h;
     std::vector<dsm::CamStatic> light_cams_h;
@@ -40,13 +42,24 @@ struct dsm_plan {
     int *scene_vert_off_d = nullptr;    // [B+1]
     int *pose_counts_d = nullptr;       // [B]
     float *pose_centers_d = nullptr;    // [B,3]
+    int *cam_renders_off_d = nullptr;   // [Cm+1] renders of each camera view
+    int *cam_renders_d = nullptr;
+    int *scene_views_off_d = nullptr;   // [B+1] views of each scene
+    int *scene_views_d = nullptr;
+    int *vc_off_d = nullptr;            // [V+1] triangle corners of each vertex
+    int *vc_list_d = nullptr;           // (scene-local face << 2) | corner
+    int *light_renders_off_d = nullptr; // [L+1] (render << 5 | slot) using each light
+    int *light_renders_d = nullptr;
+    int *scene_face_off_d = nullptr;    // [B+1]
 
     // layout of the caller's saved buffer (byte offsets)
     size_t sv_keys = 0, sv_clip = 0, sv_setup = 0, sv_F0 = 0, sv_M = 0, sv_img0 = 0, saved_bytes = 0;
     // layout of the caller's scratch buffer (byte offsets)
     size_t sc_counters = 0, sc_pair_cnt = 0, sc_pair_off = 0, sc_scan = 0, sc_tile_cnt = 0, sc_tile_start = 0,
            sc_tile_cursor = 0, sc_bins = 0, sc_overflow = 0, sc_F1 = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
-           sc_gclip = 0, sc_glight = 0, sc_galbedo = 0, sc_zero_fwd_end = 0, scratch_bytes = 0;
+           sc_gclip = 0, sc_glight = 0, sc_zero_fwd_end = 0, sc_bigcount = 0, sc_zero_bwd_end = 0,
+           sc_pair_sums = 0, sc_gtri = 0, sc_biglist = 0, sc_part_light = 0, sc_part_gm = 0, sc_part_render = 0,
+           scratch_bytes = 0;
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
