@@ -8,7 +8,8 @@
 // O are exit edges; the first one crossed on the way F -> O (smallest
 // float32 ratio E(F) / (E(F) - E(O)), lower edge index on ties) is taken.
 // The pair is smoothed only if that edge is a silhouette in the view
-// (boundary, non-manifold, or neighbour of opposite facing) and, so that
+// (boundary, non-manifold, or neighbour of opposite facing; precomputed per
+// triangle as TriSetup::sil) and, so that
 // each edge is handled in one direction only, |dY| > |dX| for horizontal
 // pairs and |dY| <= |dX| for vertical ones.  The continuous crossing
 // alpha = E(F) / (E(F) - E(O)) is computed from the unsnapped vertex
@@ -57,6 +58,7 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     const int fi = self_is_front ? is : in_, fj = self_is_front ? js : jn;
     const int oi = self_is_front ? in_ : is, oj = self_is_front ? jn : js;
     const TriSetup &S = setup[v.setup_off + t];
+    if (S.sil == 0) return false;              // no silhouette edge to cross
     const int fX = fi * kSub + kSub / 2, fY = fj * kSub + kSub / 2;
     const int oX = oi * kSub + kSub / 2, oY = oj * kSub + kSub / 2;
     float best = 0.f;
@@ -76,13 +78,10 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     const int dX = S.X[b] - S.X[a], dY = S.Y[b] - S.Y[a];
     const bool dir_ok = horiz ? (abs(dY) > abs(dX)) : (abs(dY) <= abs(dX));
     if (!dir_ok) return false;
+    if (!((S.sil >> ebest) & 1)) return false;
     const bool sw = S.swapped != 0;
     const int oa = orig_slot(a, sw), ob = orig_slot(b, sw);
-    const int k = 3 - oa - ob;
     const size_t fidx = (size_t)(v.face_off + (int)t);
-    const int nb = adj[3 * fidx + k];
-    const bool sil = nb < 0 || setup[v.setup_off + nb].facing != S.facing;
-    if (!sil) return false;
     out.va = faces[3 * fidx + oa];
     out.vb = faces[3 * fidx + ob];
     double ca[4], cb[4];

@@ -452,6 +452,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_setup(p->views_d, p->nviews, p->max_faces, p->faces_d, clip, setup, pair_cnt, p->tile, cnt, s));
+    DSM_TRY(launch_silhouettes(p->views_d, p->nviews, p->max_faces, p->adj_d, setup, s));
     DSM_TRY(launch_scan(pair_cnt, pair_off, scan, p->ntri, s));
     DSM_TRY(launch_binning(p->views_d, setup, pair_off, p->ntri, p->capacity, p->tile, tile_cnt, tile_start,
                            tile_cursor, scan, p->ntiles, bins, overflow, cnt, s));

@@ -61,103 +61,102 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
     const float *src = in + J.in_off + map_shift;
     float *dst = out + J.out_off + map_shift;
 
-    for (int idx = tid; idx < RH * RW; idx += kBlurThreads) {
-        const int ly = idx / RW, lx = idx - ly * RW;
-        int gx = x0 - r + lx, gy = y0 - r + ly;
-        float a, b;
-        if (!ADJ) {
-            gx = min(max(gx, 0), S - 1);
-            gy = min(max(gy, 0), S - 1);
-            const size_t o = (size_t)gy * S + gx;
-            a = src[o];
-            b = src[plane + o];
-        } else {
-            const bool ok = gx >= 0 && gx < S && gy >= 0 && gy < S;
-            const size_t o = ok ? (size_t)gy * S + gx : 0;
-            a = ok ? src[o] : 0.f;
-            b = ok ? src[plane + o] : 0.f;
+    // thread (cx, cy): cx = lane column 0..63, cy = row phase 0..3; no integer division
+    const int cx = tid & 63, cy = tid >> 6;
+    for (int ly = cy; ly < RH; ly += 4) {
+        int gy = y0 - r + ly;
+        bool rok = true;
+        if (!ADJ) gy = min(max(gy, 0), S - 1);
+        else rok = gy >= 0 && gy < S;
+        const size_t rowo = (size_t)(rok ? gy : 0) * S;
+        for (int lx = cx; lx < RW; lx += 64) {
+            int gx = x0 - r + lx;
+            bool ok = rok;
+            if (!ADJ) gx = min(max(gx, 0), S - 1);
+            else ok = ok && gx >= 0 && gx < S;
+            const size_t o = rowo + (ok ? gx : 0);
+            sin0[ly * RW + lx] = ok ? src[o] : 0.f;
+            sin0[RH * RW + ly * RW + lx] = ok ? src[plane + o] : 0.f;
         }
-        sin0[idx] = a;
-        sin0[RH * RW + idx] = b;
     }
     __syncthreads();
 
     if (!ADJ) {
         // horizontal pass over all staged rows
-        for (int idx = tid; idx < RH * kBlurTX; idx += kBlurThreads) {
-            const int ly = idx / kBlurTX, lx = idx - ly * kBlurTX;
-            const float *ra = sin0 + ly * RW + lx;
+        for (int ly = cy; ly < RH; ly += 4) {
+            const float *ra = sin0 + ly * RW + cx;
             const float *rb = ra + RH * RW;
-            float a = 0.f, b = 0.f;
-            for (int j = 0; j < k; ++j) { a += w[j] * ra[j]; b += w[j] * rb[j]; }
-            mid0[idx] = a;
-            mid0[RH * kBlurTX + idx] = b;
+            float a = 0.f, bb = 0.f;
+            for (int j = 0; j < k; ++j) { a += w[j] * ra[j]; bb += w[j] * rb[j]; }
+            mid0[ly * kBlurTX + cx] = a;
+            mid0[RH * kBlurTX + ly * kBlurTX + cx] = bb;
         }
         __syncthreads();
-        // vertical pass, one output texel per (thread, step)
-        for (int idx = tid; idx < TY * kBlurTX; idx += kBlurThreads) {
-            const int ly = idx / kBlurTX, lx = idx - ly * kBlurTX;
-            const int gx = x0 + lx, gy = y0 + ly;
+        // vertical pass
+        const int gx = x0 + cx;
+        for (int ly = cy; ly < TY; ly += 4) {
+            const int gy = y0 + ly;
             if (gx >= S || gy >= S) continue;
-            const float *ca = mid0 + ly * kBlurTX + lx;
+            const float *ca = mid0 + ly * kBlurTX + cx;
             const float *cb = ca + RH * kBlurTX;
-            float a = 0.f, b = 0.f;
-            for (int j = 0; j < k; ++j) { a += w[j] * ca[j * kBlurTX]; b += w[j] * cb[j * kBlurTX]; }
+            float a = 0.f, bb = 0.f;
+            for (int j = 0; j < k; ++j) { a += w[j] * ca[j * kBlurTX]; bb += w[j] * cb[j * kBlurTX]; }
             const size_t o = (size_t)gy * S + gx;
             dst[o] = a;
-            dst[plane + o] = b;
+            dst[plane + o] = bb;
         }
     } else {
         // transpose of the vertical pass: rows [0, TY), all staged columns
-        for (int idx = tid; idx < TY * RW; idx += kBlurThreads) {
-            const int ly = idx / RW, lx = idx - ly * RW;
+        for (int ly = cy; ly < TY; ly += 4) {
             const int gy = y0 + ly;
-            const float *ca = sin0 + ly * RW + lx;
-            const float *cb = ca + RH * RW;
-            float a = 0.f, b = 0.f;
-            for (int j = 0; j < k; ++j) { a += w[j] * ca[j * RW]; b += w[j] * cb[j * RW]; }
-            if (gy == 0) {             // taps clamped onto row 0: sum_{i<r} g[i] * cum(r-1-i)
-                for (int i = 0; i < r; ++i) {
-                    const int l = (i - y0 + r) * RW + lx;
-                    a += cum[r - 1 - i] * sin0[l];
-                    b += cum[r - 1 - i] * sin0[RH * RW + l];
+            for (int lx = cx; lx < RW; lx += 64) {
+                const float *ca = sin0 + ly * RW + lx;
+                const float *cb = ca + RH * RW;
+                float a = 0.f, bb = 0.f;
+                for (int j = 0; j < k; ++j) { a += w[j] * ca[j * RW]; bb += w[j] * cb[j * RW]; }
+                if (gy == 0) {             // taps clamped onto row 0: sum_{i<r} g[i] * cum(r-1-i)
+                    for (int i = 0; i < r; ++i) {
+                        const int l = (i - y0 + r) * RW + lx;
+                        a += cum[r - 1 - i] * sin0[l];
+                        bb += cum[r - 1 - i] * sin0[RH * RW + l];
+                    }
                 }
-            }
-            if (gy == S - 1) {         // taps clamped onto the last row
-                for (int i = S - r; i < S; ++i) {
-                    const int l = (i - y0 + r) * RW + lx;
-                    a += cum[r - 1 - (S - 1 - i)] * sin0[l];
-                    b += cum[r - 1 - (S - 1 - i)] * sin0[RH * RW + l];
+                if (gy == S - 1) {         // taps clamped onto the last row
+                    for (int i = S - r; i < S; ++i) {
+                        const int l = (i - y0 + r) * RW + lx;
+                        a += cum[r - 1 - (S - 1 - i)] * sin0[l];
+                        bb += cum[r - 1 - (S - 1 - i)] * sin0[RH * RW + l];
+                    }
                 }
+                mid0[ly * RW + lx] = a;
+                mid0[TY * RW + ly * RW + lx] = bb;
             }
-            mid0[idx] = a;
-            mid0[TY * RW + idx] = b;
         }
         __syncthreads();
-        for (int idx = tid; idx < TY * kBlurTX; idx += kBlurThreads) {
-            const int ly = idx / kBlurTX, lx = idx - ly * kBlurTX;
-            const int gx = x0 + lx, gy = y0 + ly;
+        const int gx = x0 + cx;
+        for (int ly = cy; ly < TY; ly += 4) {
+            const int gy = y0 + ly;
             if (gx >= S || gy >= S) continue;
-            const float *ra = mid0 + ly * RW + lx;
+            const float *ra = mid0 + ly * RW + cx;
             const float *rb = ra + TY * RW;
-            float a = 0.f, b = 0.f;
-            for (int j = 0; j < k; ++j) { a += w[j] * ra[j]; b += w[j] * rb[j]; }
+            float a = 0.f, bb = 0.f;
+            for (int j = 0; j < k; ++j) { a += w[j] * ra[j]; bb += w[j] * rb[j]; }
             // global column i sits at ra[i - gx + r]
             if (gx == 0) {
                 for (int i = 0; i < r; ++i) {
                     a += cum[r - 1 - i] * ra[i + r];
-                    b += cum[r - 1 - i] * rb[i + r];
+                    bb += cum[r - 1 - i] * rb[i + r];
                 }
             }
             if (gx == S - 1) {
                 for (int i = S - r; i < S; ++i) {
                     a += cum[r - 1 - (S - 1 - i)] * ra[i - gx + r];
-                    b += cum[r - 1 - (S - 1 - i)] * rb[i - gx + r];
+                    bb += cum[r - 1 - (S - 1 - i)] * rb[i - gx + r];
                 }
             }
             const size_t o = (size_t)gy * S + gx;
             dst[o] = a;
-            dst[plane + o] = b;
+            dst[plane + o] = bb;
         }
     }
 }

@@ -60,7 +60,8 @@ struct TriSetup {
     unsigned short bx0, by0, bx1, by1;  // inclusive pixel bbox, clipped to the view
     signed char facing;          // +1 / -1 orientation before re-orienting, 0 if not rasterized
     unsigned char swapped;       // 2nd and 3rd vertex exchanged
-    unsigned char pad0, pad1;
+    unsigned char sil;           // bit e: oriented edge e is a silhouette in this view
+    unsigned char pad1;
     int pad2[2];
 };
 static_assert(sizeof(TriSetup) == 64, "TriSetup must stay 64 bytes");
@@ -87,10 +88,38 @@ struct DevCounters {
 
 // ----------------------------------------------------------------------------- helpers
 
+// Sum over the 64 lanes of a wave, returned to every lane.  DPP moves inside
+// each 16-lane row (quad swaps, then rotations by 4 and 8), then the four row
+// sums are read out with v_readlane.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x124>(v);   // row_ror:4
+    v += dpp_mov<0x128>(v);   // row_ror:8
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_movi(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+// Minimum over the 64 lanes of a wave, returned to every lane.  All lanes active.
+__device__ __forceinline__ int wave_min(int v) {
+    v = min(v, dpp_movi<0xB1>(v));
+    v = min(v, dpp_movi<0x4E>(v));
+    v = min(v, dpp_movi<0x124>(v));
+    v = min(v, dpp_movi<0x128>(v));
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return min(min(r0, r1), min(r2, r3));
 }
 
 __device__ __forceinline__ void atomic_add_f32(float *p, float v) {
@@ -116,6 +145,8 @@ hipError_t launch_light_param_grad(const CamStatic *cams, const float *params, c
                                    int L, hipStream_t s);
 hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
                             hipStream_t s);
+hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj, TriSetup *setup,
+                              hipStream_t s);
 hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const int *faces, const float4 *clip,
                         TriSetup *setup, unsigned *pair_count, int tile, DevCounters *counters, hipStream_t s);
 int scan_scratch_words(int n);

@@ -32,7 +32,7 @@ __device__ __forceinline__ void scatter_by_key(bool active, int key, const float
     unsigned long long pending = __ballot(active);
     while (pending) {
         const int leader = __ffsll(pending) - 1;
-        const int k = __shfl(key, leader, 64);
+        const int k = __builtin_amdgcn_readlane(key, leader);
         const bool mine = active && key == k;
         const unsigned long long m = __ballot(mine);
         pending &= ~m;
@@ -270,14 +270,22 @@ __device__ __forceinline__ void overflow_rows(const ViewConst &v, const int (&ke
 // Gradient contributions of one camera pixel: vertex terms (gv[9] for the
 // 3 corners' world positions, gc[9] for their clip (x, y, w)), albedo terms,
 // and per-light frame terms added into accl.
-template <int MAXL>
+// Where one pixel's gradient lands in a light's moment maps: the bilinear
+// taps around texel coordinate (ix + fx, iy + fy), weights for (gm1, gm2).
+struct MapHit {
+    int ix, iy;
+    float fx, fy, gm1, gm2;
+};
+
+template <int MAXL, bool DIRECT>
 __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const RenderConst &R,
                                                   const ViewConst *__restrict__ views,
                                                   const int *__restrict__ render_lights, const int *__restrict__ faces,
                                                   const float *__restrict__ verts, const float *__restrict__ albedo,
                                                   const float4 *__restrict__ clip, const float *__restrict__ maps,
                                                   float *__restrict__ gmaps, int i, int j, int tri, const float g[3],
-                                                  int C, float (&vals)[21], float (&accl)[MAXL][22]) {
+                                                  int C, float (&vals)[21], float (&accl)[MAXL][22],
+                                                  MapHit (&hits)[MAXL]) {
     const int *f = faces + 3 * (size_t)(cv.face_off + tri);
     const float px = ndc_c(i, cv.W), py = -ndc_c(j, cv.H);
     const float4 c0 = clip[cv.clip_off + f[0]], c1 = clip[cv.clip_off + f[1]], c2 = clip[cv.clip_off + f[2]];
@@ -315,6 +323,9 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         const bool inside = cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f;
         float vis = 1.f, zz = 0.f, m1 = 0.f, m2 = 0.f, var = 0.f, dd = 0.f, fx = 0.f, fy = 0.f;
         long long o00 = 0, o01 = 0, o10 = 0, o11 = 0;
+        int ixs = 0, iys = 0;
+        hits[q].gm1 = 0.f;
+        hits[q].gm2 = 0.f;
         const int S = l.W;
         const float *ma = maps + l.map_off, *mb = maps + l.map_off + (long long)S * S;
         if (inside) {
@@ -324,6 +335,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             fx = sx - fx0;
             fy = sy - fy0;
             const int ix = (int)fx0, iy = (int)fy0;
+            ixs = ix;
+            iys = iy;
             const int x0 = min(max(ix, 0), S - 1), x1 = min(max(ix + 1, 0), S - 1);
             const int y0 = min(max(iy, 0), S - 1), y1 = min(max(iy + 1, 0), S - 1);
             const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
@@ -393,12 +406,16 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                 gl[16] -= gdepth * ux_; gl[17] -= gdepth * uy_; gl[18] -= gdepth * uz_;
             }
             // bilinear scatter to the moment maps
-            float *ga = gmaps + l.map_off, *gb = gmaps + l.map_off + (long long)S * S;
-            const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
-            atomic_add_f32(ga + o00, gm1 * w00); atomic_add_f32(ga + o01, gm1 * w01);
-            atomic_add_f32(ga + o10, gm1 * w10); atomic_add_f32(ga + o11, gm1 * w11);
-            atomic_add_f32(gb + o00, gm2 * w00); atomic_add_f32(gb + o01, gm2 * w01);
-            atomic_add_f32(gb + o10, gm2 * w10); atomic_add_f32(gb + o11, gm2 * w11);
+            if (DIRECT) {
+                float *ga = gmaps + l.map_off, *gb = gmaps + l.map_off + (long long)S * S;
+                const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
+                atomic_add_f32(ga + o00, gm1 * w00); atomic_add_f32(ga + o01, gm1 * w01);
+                atomic_add_f32(ga + o10, gm1 * w10); atomic_add_f32(ga + o11, gm1 * w11);
+                atomic_add_f32(gb + o00, gm2 * w00); atomic_add_f32(gb + o01, gm2 * w01);
+                atomic_add_f32(gb + o10, gm2 * w10); atomic_add_f32(gb + o11, gm2 * w11);
+            } else {
+                hits[q] = MapHit{ixs, iys, fx, fy, gm1, gm2};
+            }
             // the map position moves with x and with the light camera
             const float dm1fx = (1.f - fy) * (ma[o01] - ma[o00]) + fy * (ma[o11] - ma[o10]);
             const float dm1fy = (1.f - fx) * (ma[o10] - ma[o00]) + fx * (ma[o11] - ma[o01]);
@@ -440,6 +457,66 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
     bary_backward(b, px, py, gb0, gb1, gb2, gc);
 #pragma unroll
     for (int k = 0; k < 9; ++k) vals[9 + k] = gc[k];
+}
+
+// Bilinear scatter of one light's moment-map gradient from the pixels of a
+// tile.  Each wave adds its taps into an LDS window of WIN x WIN texels
+// anchored at the smallest tap it touches, then adds the window's non-zero
+// texels to global memory: a few texels per pixel instead of eight atomics.
+// Taps outside the window go to global memory directly.  Uniform call.
+template <int NW, int PPT, int WIN>
+__device__ __forceinline__ void map_window_scatter(const MapHit (&hit)[PPT], int S, float *__restrict__ gmap) {
+    __shared__ float win[NW][2][WIN * WIN];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int mx = 0x7fffffff, my = 0x7fffffff;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (hit[k].gm1 != 0.f || hit[k].gm2 != 0.f) {
+            mx = min(mx, min(max(hit[k].ix, 0), S - 1));
+            my = min(my, min(max(hit[k].iy, 0), S - 1));
+        }
+    mx = wave_min(mx);
+    my = wave_min(my);
+    const bool any = mx != 0x7fffffff;
+    for (int e = lane; e < 2 * WIN * WIN; e += 64) (&win[w][0][0])[e] = 0.f;
+    __syncthreads();
+    const long long plane = (long long)S * S;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const MapHit &h = hit[k];
+        if (h.gm1 == 0.f && h.gm2 == 0.f) continue;
+        const int x0 = min(max(h.ix, 0), S - 1), x1 = min(max(h.ix + 1, 0), S - 1);
+        const int y0 = min(max(h.iy, 0), S - 1), y1 = min(max(h.iy + 1, 0), S - 1);
+        const float w00 = (1.f - h.fx) * (1.f - h.fy), w01 = h.fx * (1.f - h.fy);
+        const float w10 = (1.f - h.fx) * h.fy, w11 = h.fx * h.fy;
+        if (x1 - mx < WIN && y1 - my < WIN) {
+            float *a = win[w][0], *b = win[w][1];
+            const int o00 = (y0 - my) * WIN + (x0 - mx), o01 = (y0 - my) * WIN + (x1 - mx);
+            const int o10 = (y1 - my) * WIN + (x0 - mx), o11 = (y1 - my) * WIN + (x1 - mx);
+            atomicAdd(a + o00, h.gm1 * w00); atomicAdd(a + o01, h.gm1 * w01);
+            atomicAdd(a + o10, h.gm1 * w10); atomicAdd(a + o11, h.gm1 * w11);
+            atomicAdd(b + o00, h.gm2 * w00); atomicAdd(b + o01, h.gm2 * w01);
+            atomicAdd(b + o10, h.gm2 * w10); atomicAdd(b + o11, h.gm2 * w11);
+        } else {
+            float *a = gmap, *b = gmap + plane;
+            const long long o00 = (long long)y0 * S + x0, o01 = (long long)y0 * S + x1;
+            const long long o10 = (long long)y1 * S + x0, o11 = (long long)y1 * S + x1;
+            atomic_add_f32(a + o00, h.gm1 * w00); atomic_add_f32(a + o01, h.gm1 * w01);
+            atomic_add_f32(a + o10, h.gm1 * w10); atomic_add_f32(a + o11, h.gm1 * w11);
+            atomic_add_f32(b + o00, h.gm2 * w00); atomic_add_f32(b + o01, h.gm2 * w01);
+            atomic_add_f32(b + o10, h.gm2 * w10); atomic_add_f32(b + o11, h.gm2 * w11);
+        }
+    }
+    __syncthreads();
+    if (any)
+        for (int e = lane; e < WIN * WIN; e += 64) {
+            const int gx = mx + e % WIN, gy = my + e / WIN;
+            if (gx >= S || gy >= S) continue;
+            const long long o = (long long)gy * S + gx;
+            atomic_add_f32(gmap + o, win[w][0][e]);
+            atomic_add_f32(gmap + plane + o, win[w][1][e]);
+        }
+    __syncthreads();
 }
 
 template <int T, int MAXL>
@@ -484,19 +561,34 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
         for (int q = 0; q < MAXL; ++q)
 #pragma unroll
             for (int i = 0; i < 22; ++i) accl[q][i] = 0.f;
+        constexpr bool kDirect = TS::PPT * MAXL > 4;     // register budget for deferred map taps
+        MapHit hits[TS::PPT][MAXL];
 #pragma unroll
         for (int k = 0; k < TS::PPT; ++k) {
+#pragma unroll
+            for (int q = 0; q < MAXL; ++q) hits[k][q] = MapHit{0, 0, 0.f, 0.f, 0.f, 0.f};
             if (key[k] < 0) continue;
             const long long p = (long long)pj[k] * cv.W + pi[k];
             float g[3] = {0.f, 0.f, 0.f};
             for (int c = 0; c < C; ++c) g[c] = gimg0[R.img_off + p * C + c];
             if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) continue;
             float tmp[kNV];
-            lookup_pixel_grad<MAXL>(cv, R, views, render_lights, faces, verts, albedo, clip, maps, gmaps, pi[k], pj[k],
-                                    key[k], g, C, tmp, accl);
+            lookup_pixel_grad<MAXL, kDirect>(cv, R, views, render_lights, faces, verts, albedo, clip, maps, gmaps,
+                                             pi[k], pj[k], key[k], g, C, tmp, accl, hits[k]);
             act[k] = true;
 #pragma unroll
             for (int i = 0; i < kNV; ++i) val[k][i] += tmp[i];
+        }
+        if (!kDirect) {
+#pragma unroll
+            for (int q = 0; q < MAXL; ++q) {
+                if (q >= R.light_count) break;
+                const ViewConst &l = views[render_lights[R.light_begin + q]];
+                MapHit hq[TS::PPT];
+#pragma unroll
+                for (int k = 0; k < TS::PPT; ++k) hq[k] = hits[k][q];
+                map_window_scatter<TS::NW, TS::PPT, (T == 32 ? 32 : 16)>(hq, l.W, gmaps + l.map_off);
+            }
         }
         const int ntiles = cv.tiles_x * cv.tiles_y;
 #pragma unroll

@@ -128,7 +128,7 @@ __global__ void setup_kernel(const ViewConst *__restrict__ views, const int *__r
     for (int k = 0; k < 3; ++k) { s.X[k] = X[k]; s.Y[k] = Y[k]; s.z[k] = z[k]; }
     s.facing = valid ? (swapped ? -1 : 1) : 0;
     s.swapped = swapped ? 1 : 0;
-    s.pad0 = 0;
+    s.sil = 0;
     s.pad1 = 0;
     s.pad2[0] = view;
     s.pad2[1] = 0;
@@ -157,6 +157,27 @@ __global__ void setup_kernel(const ViewConst *__restrict__ views, const int *__r
         if (nc) atomicAdd(&counters->culled, nc);
         if (nb) atomicAdd(&counters->bad_indices, nb);
     }
+}
+
+// Silhouette mask per (view, triangle): oriented edge e is a silhouette when
+// no triangle or more than one other triangle shares it, or when the
+// neighbour across it faces the other way in this view.
+__global__ void silhouette_kernel(const ViewConst *__restrict__ views, const int *__restrict__ adj,
+                                  TriSetup *__restrict__ setup) {
+    const ViewConst &v = views[blockIdx.y];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= v.nfaces) return;
+    TriSetup &s = setup[v.setup_off + t];
+    if (s.facing == 0) return;
+    const bool sw = s.swapped != 0;
+    unsigned mask = 0;
+    for (int e = 0; e < 3; ++e) {
+        const int a = (e + 1) % 3, b = (e + 2) % 3;
+        const int oa = sw ? (a == 0 ? 0 : 3 - a) : a, ob = sw ? (b == 0 ? 0 : 3 - b) : b;
+        const int nb = adj[3 * (size_t)(v.face_off + t) + (3 - oa - ob)];
+        if (nb < 0 || setup[v.setup_off + nb].facing != s.facing) mask |= 1u << e;
+    }
+    s.sil = (unsigned char)mask;
 }
 
 // ----------------------------------------------------------------------------- scan (exclusive, uint32)
@@ -447,6 +468,13 @@ hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, c
                             hipStream_t s) {
     if (nviews == 0 || max_verts == 0) return hipSuccess;
     hipLaunchKernelGGL(transform_kernel, dim3((max_verts + 255) / 256, nviews), dim3(256), 0, s, views, verts, clip);
+    return hipGetLastError();
+}
+
+hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj, TriSetup *setup,
+                              hipStream_t s) {
+    if (nviews == 0 || max_faces == 0) return hipSuccess;
+    hipLaunchKernelGGL(silhouette_kernel, dim3((max_faces + 255) / 256, nviews), dim3(256), 0, s, views, adj, setup);
     return hipGetLastError();
 }
 

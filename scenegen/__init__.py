@@ -374,12 +374,14 @@ def config3(n_lat: int = 158, sm_res: int = 1024, view_res: int = 512,
     return Batch('multi_view', [sc], lights, cams, renders, channels=1)
 
 
-def config4(sm_res: int = 2048, width: int = 1920, height: int = 1080) -> Batch:
-    """Complex scene: 20 objects (~330k triangles), RGB albedo, 3 point lights, 1080p."""
+def config4(sm_res: int = 2048, width: int = 1920, height: int = 1080, n_objects: int = 20,
+            detail: float = 1.0) -> Batch:
+    """Complex scene: 20 objects (~330k triangles), RGB albedo, 3 point lights, 1080p.
+    n_objects / detail shrink it for tests (detail scales the tessellation)."""
     rng = np.random.default_rng(4)
     parts, albedo = [], []
     centers, radii = [], []
-    for o in range(20):
+    for o in range(n_objects):
         kind = o % 3
         scale = rng.uniform(0.3, 0.8)
         for _ in range(1000):
@@ -389,12 +391,12 @@ def config4(sm_res: int = 2048, width: int = 1920, height: int = 1080) -> Batch:
         centers.append(c)
         radii.append(scale)
         if kind == 0:
-            v, f = uv_sphere(64, 128)
+            n = max(4, int(round(64 * detail)))
+            v, f = uv_sphere(n, 2 * n)
         elif kind == 1:
-            v, f = torus(0.7, 0.3, 128, 64)
-            v = v / 1.0
+            v, f = torus(0.7, 0.3, max(6, int(round(128 * detail))), max(4, int(round(64 * detail))))
         else:
-            v, f = grid_box(37)
+            v, f = grid_box(max(1, int(round(37 * detail))))
             v = v / np.sqrt(3.0)
         v = v * scale + np.array([c[0], scale, c[1]])
         parts.append((v, f))

@@ -117,3 +117,27 @@ def test_pose_forward_and_backward():
     check_forward(b, g, o)
     normwise('gpose', g['gpose'], o['gpose'], GRAD_TOL)
     normwise('glight', g['glight'], o['glight'], GRAD_TOL)
+
+
+def cfg3_small():
+    """Multi-view: 2 point lights x 3 cameras of one displaced sphere; each
+    camera view is shared by two renders, each light by three."""
+    return sg.config3(n_lat=20, sm_res=160, view_res=120, n_cams=3, n_lights=2)
+
+
+def cfg4_small():
+    """Complex-scene shape at small size: 4 objects, RGB albedo, 3 point lights
+    summed in one render, non-square camera."""
+    return sg.config4(sm_res=192, width=200, height=112, n_objects=4, detail=0.15)
+
+
+@pytest.mark.parametrize('name', ['cfg3_small', 'cfg4_small'])
+def test_forward_and_backward_multi_view_and_rgb(name):
+    b = {'cfg3_small': cfg3_small, 'cfg4_small': cfg4_small}[name]()
+    G = random_grad(b, 7)
+    g = gpu_run(b, grad_images=G)
+    o = oracle_run(b, grad_images=G)
+    check_forward(b, g, o)
+    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
+    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
+    normwise('galbedo', g['galbedo'], o['galbedo'], GRAD_TOL)
