@@ -263,3 +263,14 @@ def test_cube_silhouette_from_light_is_closed_loop():
                     deg[v] = deg.get(v, 0) + 1
     assert nsil >= 4
     assert all(d == 2 for d in deg.values())
+
+
+def test_pose_rotation_matches_library_rotvec():
+    from scipy.spatial.transform import Rotation
+    from oracle.mesh import rodrigues
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        r = rng.normal(0, 0.7, 3)
+        R = rodrigues(torch.as_tensor(r)).numpy()
+        assert np.allclose(R, Rotation.from_rotvec(r).as_matrix(), atol=1e-14)
+    assert np.allclose(rodrigues(torch.zeros(3, dtype=torch.float64)).numpy(), np.eye(3))
