@@ -204,7 +204,6 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         cs.zfar = x.zfar;
         cs.dir_distance = x.dir_distance;
         cs.ortho_half = x.ortho_half;
-        p->blur_rmax = std::max(p->blur_rmax, (x.k - 1) / 2);
     }
     for (int c = 0; c < Cm; ++c) {
         const dsm_camera_desc &x = d->cameras[c];
@@ -263,23 +262,33 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     }
     p->capacity = (unsigned)((long long)bin_capacity_scale * (tri + tiles) / 4);
 
-    // blur jobs over all light maps, one flattened tile grid
-    int btiles = 0;
-    for (int l = 0; l < L; ++l) {
-        const dsm_light_desc &x = d->lights[l];
-        BlurJob j;
-        memset(&j, 0, sizeof(j));
-        j.S = x.resolution;
-        j.k = x.k;
-        j.in_off = p->views_h[l].map_off;
-        j.out_off = p->views_h[l].map_off;
-        j.tile_off = btiles;
-        j.tiles_x = blur_tiles_x(x.resolution);
-        filter_taps_host(x.filter, x.k, x.sigma, j.w);
-        btiles += blur_tiles(x.resolution, p->blur_rmax);
-        p->blur_jobs_h.push_back(j);
+    // blur jobs over all light maps, grouped by filter radius (one launch per radius)
+    {
+        std::vector<int> order(L);
+        for (int l = 0; l < L; ++l) order[l] = l;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return d->lights[x].k < d->lights[y].k; });
+        for (int q = 0; q < L; ++q) {
+            const int l = order[q];
+            const dsm_light_desc &x = d->lights[l];
+            const int R = (x.k - 1) / 2;
+            if (p->blur_groups.empty() || p->blur_groups.back().R != R)
+                p->blur_groups.push_back(dsm_plan::BlurGroup{R, q, 0, 0});
+            dsm_plan::BlurGroup &g = p->blur_groups.back();
+            BlurJob j;
+            memset(&j, 0, sizeof(j));
+            j.S = x.resolution;
+            j.k = x.k;
+            j.in_off = p->views_h[l].map_off;
+            j.out_off = p->views_h[l].map_off;
+            j.tile_off = g.tiles;
+            j.tiles_x = blur_tiles_x(x.resolution);
+            filter_taps_host(x.filter, x.k, x.sigma, j.w);
+            g.tiles += blur_tiles(x.resolution, R);
+            g.n += 1;
+            p->blur_jobs_h.push_back(j);
+        }
     }
-    p->blur_tiles = btiles;
 
     // saved layout
     size_t o = 0;
@@ -461,7 +470,8 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_resolve(p->views_d, p->L, p->max_light_texels, p->faces_d, verts, clip, keys, F0, s));
     DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, p->adj_d,
                               verts, keys, F0, F1, 2, s));
-    DSM_TRY(launch_blur(p->blur_jobs_d, p->L, p->blur_tiles, F1, Mm, false, p->blur_rmax, s));
+    for (const auto &g : p->blur_groups)
+        DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, F1, Mm, false, g.R, s));
     DSM_TRY(launch_lookup(p->views_d, p->renders_d, p->R, p->max_cam_pix, p->render_lights_d, p->faces_d, verts,
                           albedo, clip, keys, Mm, img0, p->C, s));
     DSM_TRY(launch_aa_forward(false, p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, p->adj_d,
@@ -505,7 +515,8 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
                                    p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
                                    p->faces_d, verts, albedo, clip, keys, Mm, gimg0, gM, setup, tile_start, bins,
                                    pair_off, pair_sums, gtri, part_render, p->C, s));
-    DSM_TRY(launch_blur(p->blur_jobs_d, p->L, p->blur_tiles, gM, gF1, true, p->blur_rmax, s));
+    for (const auto &g : p->blur_groups)
+        DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, p->adj_d, verts,
                                   clip, keys, F0, gF1, gclip, tile_start, bins, pair_off, pair_sums, gtri, part_light,
                                   s));

@@ -28,7 +28,11 @@ struct dsm_plan {
     std::vector<int> render_lights_h;
     std::vector<int> vert_off, face_off, pose_counts;
     std::vector<float> pose_centers;
-    std::vector<dsm::BlurJob> blur_jobs_h;
+    std::vector<dsm::BlurJob> blur_jobs_h;   // sorted by filter radius
+    struct BlurGroup {
+        int R, first, n, tiles;
+    };
+    std::vector<BlurGroup> blur_groups;
 
     // plan-owned device data
     dsm::ViewConst *views_d = nullptr;
