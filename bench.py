@@ -39,7 +39,9 @@ def parse():
     ap.add_argument('--res', type=int, default=512)
     ap.add_argument('--no-plain', action='store_true')
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--cpu-scenes', type=int, default=2)
+    ap.add_argument('--cpu-seconds', type=float, default=15.0,
+                    help='time budget of the oracle baseline sample')
+    ap.add_argument('--stage-reps', type=int, default=10)
     ap.add_argument('--tile', type=int, default=0)
     return ap.parse_args()
 
@@ -101,7 +103,8 @@ def main():
     assert st['culled'] == 0 and st['bad_indices'] == 0, st
 
     # ---------------- dominant kernels, timed live with HIP events on the plan's stream
-    kern = kernel_timings(plan, stream, local, poses, lp, alb, saved, scratch, images, gimg, args)
+    kern = kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, gimg, gverts, glp, galb,
+                          args)
 
     # ---------------- plain: one plan per scene, eager calls, no graph
     plain_rps = None
@@ -136,7 +139,7 @@ def main():
     # ---------------- CPU baseline: the oracle on a bounded sample of scenes
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(batch, args.cpu_scenes)
+        cpu = cpu_baseline(batch, args.cpu_seconds)
 
     out = {
         'metric': METRIC,
@@ -160,7 +163,7 @@ def main():
             'plain_renders_per_s': None if plain_rps is None else round(plain_rps, 2),
             'batched_over_plain': None if plain_rps is None else round(batched_rps / plain_rps, 3),
             'tile': int(plan.info.tile_size),
-            'kernels_us': {k: round(v['us'], 2) for k, v in kern['all'].items()},
+            'stages_us': kern['stages_us'],
         },
         'roofline': kern['roofline'],
         'cpu_baseline': cpu,
@@ -168,47 +171,81 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def kernel_timings(plan, stream, local, poses, lp, alb, saved, scratch, images, gimg, args):
-    """Average duration of the HBM-bound stages measured with HIP events on
-    `stream`: the moment filter (forward / transpose) run by the library's
-    stand-alone entry point on the batch's own maps, which launches the same
-    kernel with the same tiles as the pipeline."""
+def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, gimg, gverts, glp, galb, args):
+    """Durations of the pipeline's kernels, measured live with HIP events on
+    `stream` (the stream the kernels are launched on):
+
+    * every stage of forward + backward, eager, via the library's stage
+      timer (each targeted stage is one kernel launch);
+    * the moment filter forward / transpose again as back-to-back launches of
+      the same kernel on the batch's own smoothed maps;
+    * a plain device-to-device copy of the same size, for the achievable
+      bandwidth on this GPU.
+
+    Algorithmic bytes per launch follow the per-unit figures: filter 16 S^2
+    per map (2 channels read + written, f32); lookup P (4 + 4C) + 8 S^2 per
+    light + 12 (F + V) + 4 C F per render; lookup^T P (4 + 4C) + 16 S^2 per
+    light + 12 (F + V) + 12 V per render.
+    """
     import torch
     from paper_2308_10896_amd import dsm
+    stages = plan.time_stages(stream, verts, lp, alb, saved, scratch, images, gimg, gverts, glp, galb,
+                              args.stage_reps)
     n, S = len(plan.light_res), plan.light_res[0]
+    P = args.res * args.res
+    C = 1
+    F = np.array([len(sc.faces) for sc in batch.scenes], dtype=np.float64)
+    V = np.array([len(sc.verts) for sc in batch.scenes], dtype=np.float64)
+    R = len(batch.renders)
+    algo = {
+        'filter': 16.0 * n * S * S,
+        'filter_adj': 16.0 * n * S * S,
+        'lookup': float(R * P * (4 + 4 * C) + R * 8.0 * S * S + 12.0 * (F + V).sum() + 4.0 * C * F.sum()),
+        'lookup_adj': float(R * P * (4 + 4 * C) + R * 16.0 * S * S + 12.0 * (F + V).sum() + 12.0 * V.sum()),
+    }
+    kernels = {}
+    for name, b in algo.items():
+        us = 1000.0 * stages[name]
+        kernels[name] = dict(us=round(us, 2), bytes=b, gbs=round(b / (us * 1e-6) / 1e9, 1),
+                             frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
     reps = 20
-    res = {}
     with torch.cuda.stream(stream):
         maps = torch.stack([plan.light_maps(saved, scratch, l, 1) for l in range(n)]).contiguous()
-        for name, adj in (('moment_filter_fwd', False), ('moment_filter_adj', True)):
+        for name, adj in (('filter', False), ('filter_adj', True)):
             for _ in range(3):
                 dsm.filter_moments(maps, 'box', 5, 0.0, adj)
             t = timed(lambda: dsm.filter_moments(maps, 'box', 5, 0.0, adj), reps, stream)
             us = 1e6 * t / reps
-            algo = 16.0 * n * S * S           # read 2 channels + write 2 channels, float32
-            res[name] = dict(us=us, bytes=algo, gbs=algo / (us * 1e-6) / 1e9)
-    dom = res['moment_filter_fwd']
-    roof = {'kernel': 'blur_kernel (moment filter forward, 64 maps x 2 x 512^2 f32, 5x5 box)',
-            'bound': 'hbm', 'achieved': round(dom['gbs'], 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
-            'frac': round(dom['gbs'] / HBM_PEAK_GBS, 4), 'traffic': None,
-            'adjoint_achieved': round(res['moment_filter_adj']['gbs'], 1)}
-    return {'all': res, 'roofline': roof}
+            kernels[name]['us_back_to_back'] = round(us, 2)
+            kernels[name]['gbs_back_to_back'] = round(algo[name] / (us * 1e-6) / 1e9, 1)
+        dst = torch.empty_like(maps)
+        for _ in range(3):
+            dst.copy_(maps)
+        t = timed(lambda: dst.copy_(maps), reps, stream)
+        copy_gbs = 2.0 * maps.numel() * 4 / (t / reps) / 1e9
+    dom = max(kernels, key=lambda k: kernels[k]['us'])
+    d = kernels[dom]
+    roof = {'kernel': dom, 'bound': 'hbm', 'achieved': d['gbs'], 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+            'frac': d['frac'], 'traffic': None,
+            'kernels': kernels,
+            'copy_gbs': round(copy_gbs, 1)}
+    return {'stages_us': {k: round(1000.0 * v, 2) for k, v in stages.items()}, 'roofline': roof}
 
 
-def cpu_baseline(batch, n_scenes):
-    """The oracle (float64, plain numpy/torch) timed on this host's cores for
-    fwd+bwd of a bounded sample of the batch's renders."""
+def cpu_baseline(batch, budget_s):
+    """The oracle (float64, plain numpy/torch) timed on this host's cores:
+    fwd+bwd of the batch's scenes, smallest first and then in a seeded
+    order, until `budget_s` seconds have passed."""
     import torch
     import scenegen as sg
     from oracle import pipeline as P
-    threads = os.cpu_count() or 1
-    torch.set_num_threads(threads)
+    threads = torch.get_num_threads()
     tris = np.array([len(s.faces) for s in batch.scenes])
-    order = np.argsort(tris)
-    pick = [int(order[0])] + [int(i) for i in np.random.default_rng(1).choice(len(tris), max(0, n_scenes - 1),
-                                                                              replace=False)]
+    first = int(np.argmin(tris))
+    rest = [int(i) for i in np.random.default_rng(1).permutation(len(tris)) if int(i) != first]
+    done = []
     t0 = time.time()
-    for i in pick:
+    for i in [first] + rest:
         b1 = sg.Batch(batch.name, [batch.scenes[i]], [sg.Light(**{**batch.lights[i].__dict__, 'scene': 0})],
                       [sg.Camera(**{**batch.cameras[i].__dict__, 'scene': 0})], [sg.Render(0, [0])], channels=1,
                       target_poses=[np.zeros(6, np.float32)])
@@ -216,11 +253,14 @@ def cpu_baseline(batch, n_scenes):
         out = P.render(b1, P.world_vertices(b1, base, poses), lp, alb)
         loss = sum((im ** 2).sum() for im in out['images'])
         loss.backward()
+        done.append(i)
+        if time.time() - t0 >= budget_s:
+            break
     dt = time.time() - t0
-    return {'value': round(len(pick) / dt, 4), 'unit': 'renders/s', 'cores': int(torch.get_num_threads()),
+    return {'value': round(len(done) / dt, 4), 'unit': 'renders/s', 'cores': int(threads),
             'kind': 'oracle',
-            'sample': f'{len(pick)} of the {len(batch.scenes)} scenes (smallest + seeded random: '
-                      f'{[int(tris[i]) for i in pick]} triangles), fwd+bwd each, float64, {dt:.1f} s'}
+            'sample': f'{len(done)} of the {len(batch.scenes)} scenes (smallest first, then seeded order; '
+                      f'{int(tris[done].sum())} triangles in all), fwd+bwd each in float64, {dt:.1f} s'}
 
 
 if __name__ == '__main__':

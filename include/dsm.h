@@ -257,6 +257,47 @@ dsm_status dsm_get_stats(const dsm_plan *plan, const void *scratch_dev, dsm_stat
 dsm_status dsm_filter_moments(int32_t S, int32_t n_maps, int32_t filter, int32_t k, float sigma,
                               const float *in_dev, float *out_dev, int32_t adjoint, dsm_stream stream);
 
+/*
+ * Stage timing (instrumentation, not part of the method).  The pipeline's
+ * stages in launch order; a stage's time runs from its first launch to the
+ * next stage's first launch on the stream.
+ */
+typedef enum {
+    DSM_STAGE_SETUP = 0,        /* zero fills, light frames, transform, triangle setup, silhouette masks */
+    DSM_STAGE_BIN,              /* (triangle, tile) pair scan and tile binning */
+    DSM_STAGE_RASTER,           /* tile raster of every light and camera view (a2-a3, a7) */
+    DSM_STAGE_RESOLVE,          /* light-view moment resolve (z, z^2) */
+    DSM_STAGE_LIGHT_AA,         /* light-view edge smoothing */
+    DSM_STAGE_FILTER,           /* moment filter G (Alg. 1) */
+    DSM_STAGE_LOOKUP,           /* Chebyshev visibility + Lambert shading (Alg. 2) */
+    DSM_STAGE_CAMERA_AA,        /* camera-view edge smoothing */
+    DSM_STAGE_BWD_SETUP,        /* zero fills, light frames */
+    DSM_STAGE_CAMERA_AA_ADJ,    /* camera-view smoothing^T */
+    DSM_STAGE_LOOKUP_ADJ,       /* lookup + shading^T, map-gradient scatter, per-(triangle, tile) sums */
+    DSM_STAGE_FILTER_ADJ,       /* G^T */
+    DSM_STAGE_LIGHT_ADJ,        /* light-view smoothing^T + resolve^T */
+    DSM_STAGE_VERTEX_GRAD,      /* per-triangle reduction, vertex and albedo gathers */
+    DSM_STAGE_LIGHT_GRAD,       /* light partial reduction and light-parameter chain */
+    DSM_STAGE_COUNT
+} dsm_stage;
+#define DSM_MAX_TIMING_REPS 1000
+
+/*
+ * Runs dsm_forward + dsm_backward `reps` times on `stream` (arguments as
+ * there) with a HIP event at every stage boundary, waits for the stream, and
+ * writes each stage's mean duration in milliseconds to ms_out (host,
+ * [DSM_STAGE_COUNT]).  `stream` must be a non-null stream that is not being
+ * captured.  Outputs are those of the last repetition.  Errors:
+ * DSM_ERR_INVALID_ARG for a null plan/ms_out/stream or reps outside
+ * [1, DSM_MAX_TIMING_REPS]; buffer errors as dsm_forward; DSM_ERR_HIP when an
+ * event cannot be created, recorded or read.
+ */
+dsm_status dsm_time_stages(dsm_plan *plan, const float *verts_dev, const float *light_params_dev,
+                           const float *albedo_dev, void *saved_dev, size_t saved_bytes, void *scratch_dev,
+                           size_t scratch_bytes, float *images_dev, const float *grad_images_dev,
+                           float *grad_verts_dev, float *grad_light_params_dev, float *grad_albedo_dev,
+                           int32_t reps, float *ms_out, dsm_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,7 +58,7 @@ def rodrigues(r):
         torch.stack([-r[1], r[0], torch.zeros((), dtype=r.dtype)]),
     ])
     I = torch.eye(3, dtype=r.dtype)
-    if float(th2) < 1e-24:
+    if float(th2.detach()) < 1e-24:
         return I + K
     return I + torch.sin(th) / th * K + (1 - torch.cos(th)) / th2 * (K @ K)
 

@@ -87,6 +87,7 @@ _SIGNATURES = {
     'dsm_get_render_image0': (C.c_int, [P, P, I32, P, P]),
     'dsm_get_stats': (C.c_int, [P, P, C.POINTER(Stats), P]),
     'dsm_filter_moments': (C.c_int, [I32, I32, I32, I32, F32, P, P, I32, P]),
+    'dsm_time_stages': (C.c_int, [P, P, P, P, P, SZ, P, SZ, P, P, P, P, P, I32, C.POINTER(C.c_float), P]),
 }
 
 _lib = None

@@ -47,7 +47,7 @@ __device__ __forceinline__ void clip_f64(const float *M, const float *p, double 
 // the pair is not smoothed.  keys: this view's key array base.
 template <bool WANT_GRAD>
 __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__restrict__ setup,
-                                        const int *__restrict__ faces, const int *__restrict__ adj,
+                                        const int *__restrict__ faces, const unsigned char *__restrict__ silm,
                                         const float *__restrict__ verts, unsigned long long ks,
                                         unsigned long long kn, int is, int js, int in_, int jn, bool horiz,
                                         bool &self_is_front, AAPair &out) {
@@ -57,8 +57,8 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     const unsigned t = self_is_front ? ts : tn;
     const int fi = self_is_front ? is : in_, fj = self_is_front ? js : jn;
     const int oi = self_is_front ? in_ : is, oj = self_is_front ? jn : js;
+    if (silm[v.setup_off + t] == 0) return false;   // no silhouette edge to cross
     const TriSetup &S = setup[v.setup_off + t];
-    if (S.sil == 0) return false;              // no silhouette edge to cross
     const int fX = fi * kSub + kSub / 2, fY = fj * kSub + kSub / 2;
     const int oX = oi * kSub + kSub / 2, oY = oj * kSub + kSub / 2;
     float best = 0.f;

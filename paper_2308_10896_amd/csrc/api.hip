@@ -295,6 +295,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sv_keys = o; o = align_up(o + 8 * (size_t)pix);
     p->sv_clip = o; o = align_up(o + 16 * (size_t)clip);
     p->sv_setup = o; o = align_up(o + sizeof(TriSetup) * (size_t)tri);
+    p->sv_sil = o; o = align_up(o + (size_t)tri);
     p->sv_F0 = o; o = align_up(o + 4 * (size_t)maps);
     p->sv_M = o; o = align_up(o + 4 * (size_t)maps);
     p->sv_img0 = o; o = align_up(o + 4 * (size_t)img);
@@ -438,8 +439,14 @@ T *at(void *base, size_t off) { return (T *)((char *)base + off); }
 template <class T>
 const T *at(const void *base, size_t off) { return (const T *)((const char *)base + off); }
 
+// marks (nullable): events recorded at stage boundaries; marks[i] opens stage i.
+#define DSM_MARK(i)                                                      \
+    do {                                                                 \
+        if (marks) DSM_TRY(hipEventRecord(marks[(i)], s));              \
+    } while (0)
+
 dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo, void *saved,
-                           void *scratch, float *images, hipStream_t s) {
+                           void *scratch, float *images, hipStream_t s, hipEvent_t *marks = nullptr) {
     DevCounters *cnt = at<DevCounters>(scratch, p->sc_counters);
     unsigned *tile_cnt = at<unsigned>(scratch, p->sc_tile_cnt);
     unsigned *tile_cursor = at<unsigned>(scratch, p->sc_tile_cursor);
@@ -453,38 +460,48 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
     float4 *clip = at<float4>(saved, p->sv_clip);
     TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
+    unsigned char *silm = at<unsigned char>(saved, p->sv_sil);
     float *F0 = at<float>(saved, p->sv_F0);
     float *Mm = at<float>(saved, p->sv_M);
     float *img0 = at<float>(saved, p->sv_img0);
 
+    DSM_MARK(DSM_STAGE_SETUP);
     DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_setup(p->views_d, p->nviews, p->max_faces, p->faces_d, clip, setup, pair_cnt, p->tile, cnt, s));
-    DSM_TRY(launch_silhouettes(p->views_d, p->nviews, p->max_faces, p->adj_d, setup, s));
+    DSM_TRY(launch_silhouettes(p->views_d, p->nviews, p->max_faces, p->adj_d, setup, silm, s));
+    DSM_MARK(DSM_STAGE_BIN);
     DSM_TRY(launch_scan(pair_cnt, pair_off, scan, p->ntri, s));
     DSM_TRY(launch_binning(p->views_d, setup, pair_off, p->ntri, p->capacity, p->tile, tile_cnt, tile_start,
                            tile_cursor, scan, p->ntiles, bins, overflow, cnt, s));
+    DSM_MARK(DSM_STAGE_RASTER);
     DSM_TRY(launch_raster(p->views_d, p->tile_view_d, p->ntiles, p->tile, setup, tile_start, bins, overflow, cnt, cnt,
                           keys, s));
+    DSM_MARK(DSM_STAGE_RESOLVE);
     DSM_TRY(launch_resolve(p->views_d, p->L, p->max_light_texels, p->faces_d, verts, clip, keys, F0, s));
-    DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, p->adj_d,
+    DSM_MARK(DSM_STAGE_LIGHT_AA);
+    DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, silm,
                               verts, keys, F0, F1, 2, s));
+    DSM_MARK(DSM_STAGE_FILTER);
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, F1, Mm, false, g.R, s));
+    DSM_MARK(DSM_STAGE_LOOKUP);
     DSM_TRY(launch_lookup(p->views_d, p->renders_d, p->R, p->max_cam_pix, p->render_lights_d, p->faces_d, verts,
                           albedo, clip, keys, Mm, img0, p->C, s));
-    DSM_TRY(launch_aa_forward(false, p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, p->adj_d,
+    DSM_MARK(DSM_STAGE_CAMERA_AA);
+    DSM_TRY(launch_aa_forward(false, p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
                               verts, keys, img0, images, p->C, s));
     return DSM_OK;
 }
 
 dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
                             const void *saved, void *scratch, const float *gimg, float *gverts, float *glparams,
-                            float *galbedo, hipStream_t s) {
+                            float *galbedo, hipStream_t s, hipEvent_t *marks = nullptr) {
     const unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
     const float4 *clip = at<float4>(saved, p->sv_clip);
     const TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
+    const unsigned char *silm = at<unsigned char>(saved, p->sv_sil);
     const float *F0 = at<float>(saved, p->sv_F0);
     const float *Mm = at<float>(saved, p->sv_M);
     const float *img0 = at<float>(saved, p->sv_img0);
@@ -506,27 +523,35 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     float *part_gm = at<float>(scratch, p->sc_part_gm);
     float *part_render = at<float>(scratch, p->sc_part_render);
 
+    DSM_MARK(DSM_STAGE_BWD_SETUP);
     DSM_TRY(zero_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, s));   // big count, gM, silhouette gclip
     DSM_TRY(launch_overflow_rows_zero(overflow, cnt, gtri, s));
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
-    DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, p->adj_d,
+    DSM_MARK(DSM_STAGE_CAMERA_AA_ADJ);
+    DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
                                       verts, keys, img0, gimg, gimg0, gclip, p->C, s));
+    DSM_MARK(DSM_STAGE_LOOKUP_ADJ);
     DSM_TRY(launch_lookup_backward(p->tile, p->views_d, p->L, p->Cm, p->max_cam_tiles, p->max_lights_per_render,
                                    p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
                                    p->faces_d, verts, albedo, clip, keys, Mm, gimg0, gM, setup, tile_start, bins,
                                    pair_off, pair_sums, gtri, part_render, p->C, s));
+    DSM_MARK(DSM_STAGE_FILTER_ADJ);
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
-    DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, p->adj_d, verts,
+    DSM_MARK(DSM_STAGE_LIGHT_ADJ);
+    DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
                                   clip, keys, F0, gF1, gclip, tile_start, bins, pair_off, pair_sums, gtri, part_light,
                                   s));
+    DSM_MARK(DSM_STAGE_VERTEX_GRAD);
     DSM_TRY(launch_vertex_gradients(p->views_d, p->L, p->B, p->max_scene_verts, p->max_scene_faces, p->ntri,
                                     p->capacity, p->scene_vert_off_d, p->scene_face_off_d, p->scene_views_off_d,
                                     p->scene_views_d, p->vc_off_d, p->vc_list_d, pair_off, pair_sums, gtri, big_list,
                                     big_count, verts, gclip, gverts, part_gm, galbedo, p->C, s));
+    DSM_MARK(DSM_STAGE_LIGHT_GRAD);
     DSM_TRY(launch_glight_reduce(p->views_d, p->L, p->renders_d, p->light_renders_off_d, p->light_renders_d, part_gm,
                                  part_light, part_render, glight, s));
     DSM_TRY(launch_light_param_grad(p->light_cams_d, lparams, glight, glparams, p->L, s));
+    DSM_MARK(DSM_STAGE_COUNT);
     return DSM_OK;
 }
 
@@ -564,6 +589,44 @@ extern "C" dsm_status dsm_backward(dsm_plan *p, const float *verts, const float 
         return DSM_ERR_INVALID_ARG;
     return enqueue_backward(p, verts, lparams, albedo, saved, scratch, gimg, gverts, glparams, galbedo,
                             (hipStream_t)stream);
+}
+
+extern "C" dsm_status dsm_time_stages(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
+                                      void *saved, size_t saved_bytes, void *scratch, size_t scratch_bytes,
+                                      float *images, const float *gimg, float *gverts, float *glparams,
+                                      float *galbedo, int32_t reps, float *ms_out, dsm_stream stream) {
+    if (!p || !ms_out || reps < 1 || reps > DSM_MAX_TIMING_REPS || !stream) return DSM_ERR_INVALID_ARG;
+    dsm_status st;
+    if (!buffers_ok(p, saved, saved_bytes, scratch, scratch_bytes, &st)) return st;
+    if ((p->V_total > 0 && (!verts || !gverts)) || (p->L > 0 && (!lparams || !glparams)) ||
+        (p->F_total > 0 && !albedo) || (p->image_floats > 0 && (!images || !gimg)))
+        return DSM_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    constexpr int NE = DSM_STAGE_COUNT + 1;
+    std::vector<hipEvent_t> ev((size_t)reps * NE, nullptr);
+    dsm_status r = DSM_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { e = nullptr; r = DSM_ERR_HIP; break; }
+    for (int i = 0; i < reps && r == DSM_OK; ++i) {
+        hipEvent_t *m = ev.data() + (size_t)i * NE;
+        r = enqueue_forward(p, verts, lparams, albedo, saved, scratch, images, s, m);
+        if (r == DSM_OK)
+            r = enqueue_backward(p, verts, lparams, albedo, saved, scratch, gimg, gverts, glparams, galbedo, s, m);
+    }
+    if (r == DSM_OK && hipStreamSynchronize(s) != hipSuccess) r = DSM_ERR_HIP;
+    for (int k = 0; k < DSM_STAGE_COUNT; ++k) ms_out[k] = 0.f;
+    for (int i = 0; i < reps && r == DSM_OK; ++i)
+        for (int k = 0; k < DSM_STAGE_COUNT; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[(size_t)i * NE + k], ev[(size_t)i * NE + k + 1]) != hipSuccess) {
+                r = DSM_ERR_HIP;
+                break;
+            }
+            ms_out[k] += ms / (float)reps;
+        }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return r;
 }
 
 extern "C" dsm_status dsm_pose_forward(dsm_plan *p, const float *local, const float *poses, float *world,

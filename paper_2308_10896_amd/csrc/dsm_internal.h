@@ -146,7 +146,7 @@ hipError_t launch_light_param_grad(const CamStatic *cams, const float *params, c
 hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
                             hipStream_t s);
 hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj, TriSetup *setup,
-                              hipStream_t s);
+                              unsigned char *silm, hipStream_t s);
 hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const int *faces, const float4 *clip,
                         TriSetup *setup, unsigned *pair_count, int tile, DevCounters *counters, hipStream_t s);
 int scan_scratch_words(int n);
@@ -162,7 +162,7 @@ hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntile
 hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const int *faces, const float *verts,
                           const float4 *clip, const unsigned long long *keys, float *F0, hipStream_t s);
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
-                             const TriSetup *setup, const int *faces, const int *adj, const float *verts,
+                             const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
                              const unsigned long long *keys, const float *src, float *dst, int C, hipStream_t s);
 hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
                          const int *render_lights, const int *faces, const float *verts, const float *albedo,
@@ -170,7 +170,7 @@ hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int
                          hipStream_t s);
 // backward
 hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
-                                     const TriSetup *setup, const int *faces, const int *adj, const float *verts,
+                                     const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
                                      const unsigned long long *keys, const float *img0, const float *gimg,
                                      float *gimg0, float4 *gclip, int C, hipStream_t s);
 hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int Cm, int max_tiles, int max_lights,
@@ -181,7 +181,7 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const unsigned *bins, const unsigned *pair_off, float *pair_sums, float *gtri,
                                   float *part_render, int C, hipStream_t s);
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
-                                 const int *faces, const int *adj, const float *verts, const float4 *clip,
+                                 const int *faces, const unsigned char *silm, const float *verts, const float4 *clip,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *pair_off,
                                  float *pair_sums, float *gtri, float *part_light, hipStream_t s);

@@ -95,7 +95,7 @@ __device__ __forceinline__ void bary_backward(const BaryFull &b, float px, float
 
 __global__ __launch_bounds__(256) void aa_camera_backward_kernel(
     const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders, const TriSetup *__restrict__ setup,
-    const int *__restrict__ faces, const int *__restrict__ adj, const float *__restrict__ verts,
+    const int *__restrict__ faces, const unsigned char *__restrict__ silm, const float *__restrict__ verts,
     const unsigned long long *__restrict__ keys, const float *__restrict__ img0, const float *__restrict__ gimg,
     float *__restrict__ gimg0, float4 *__restrict__ gclip, int C) {
     const RenderConst &R = renders[blockIdx.y];
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void aa_camera_backward_kernel(
             if ((unsigned)kn == (unsigned)ks) continue;
             bool self_front;
             AAPair pr;
-            if (!aa_eval<true>(v, setup, faces, adj, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
+            if (!aa_eval<true>(v, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
             const bool self_recv = (pr.recv == 1) != self_front;
             if (self_recv) {
                 double galpha = 0;
@@ -192,9 +192,15 @@ __device__ __forceinline__ void block_sum_store(const float (&val)[N], float *ds
     }
 }
 
-// For every triangle binned to tile gt: sum of val over the tile's pixels it
-// owns -> pair_sums[pair index][0..N), zeros when it owns none.  Marks the
-// pixels whose triangle was found.  Uniform call.
+// For every triangle binned to tile gt: sum of val over the tile's active
+// pixels it owns -> pair_sums[pair index][0..N), zeros when it owns none.
+// Marks the pixels whose triangle was found.  Uniform call.
+//
+// The bin is walked in chunks of 64 entries.  Each pixel finds the entry of
+// its triangle (a broadcast LDS scan of the chunk) and adds its N values
+// into that entry's LDS row with LDS atomics; the rows are then stored
+// contiguously.  Cost per pixel is N LDS adds however many triangles share
+// the tile, so dense meshes (about one triangle per pixel) stay cheap.
 template <int T, int N>
 __device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, int tx, int ty,
                                                const TriSetup *__restrict__ setup,
@@ -202,51 +208,55 @@ __device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, int t
                                                const unsigned *__restrict__ bins, const unsigned *__restrict__ pair_off,
                                                const int (&key)[TileShape<T>::PPT],
                                                const float (&val)[TileShape<T>::PPT][N],
+                                               const bool (&act)[TileShape<T>::PPT],
                                                bool (&matched)[TileShape<T>::PPT], float *__restrict__ pair_sums) {
     using TS = TileShape<T>;
-    __shared__ float part[TS::NW][64][N];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int CH = 64;
+    __shared__ float part[CH * N];
+    __shared__ int ent[CH];
+    __shared__ unsigned slot[CH];
+    const int tid = threadIdx.x;
     const unsigned b0 = tile_start[gt], b1 = tile_start[gt + 1];
-    for (unsigned c0 = b0; c0 < b1; c0 += 64) {
-        const int n = (int)min(64u, b1 - c0);
-        for (int e = 0; e < n; ++e) {
-            const int tl = (int)(bins[c0 + e] - (unsigned)v.setup_off);
-            float acc[N];
+    bool mine = false;
 #pragma unroll
-            for (int i = 0; i < N; ++i) acc[i] = 0.f;
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < TS::PPT; ++k)
-                if (key[k] == tl) {
-                    any = true;
-                    matched[k] = true;
-#pragma unroll
-                    for (int i = 0; i < N; ++i) acc[i] += val[k][i];
-                }
-            float mine = 0.f;
-            if (__ballot(any)) {
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    const float s = wave_sum(acc[i]);
-                    if (lane == i) mine = s;
-                }
-            }
-            if (lane < N) part[w][e][lane] = mine;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < n; e += TS::NT) {
-            const unsigned si = bins[c0 + e];
+    for (int k = 0; k < TS::PPT; ++k) mine = mine || act[k];
+    const bool any = __syncthreads_or(mine) != 0;
+    for (unsigned c0 = b0; c0 < b1; c0 += CH) {
+        const int n = (int)min((unsigned)CH, b1 - c0);
+        if (tid < n) {
+            const unsigned si = bins[c0 + tid];
+            ent[tid] = (int)(si - (unsigned)v.setup_off);
             const TriSetup &st = setup[si];
             const int tx0 = st.bx0 / T, ty0 = st.by0 / T, ntx = st.bx1 / T - tx0 + 1;
-            const unsigned p = pair_off[si] + (unsigned)((ty - ty0) * ntx + (tx - tx0));
-            float *dst = pair_sums + (size_t)p * kNV;
+            slot[tid] = pair_off[si] + (unsigned)((ty - ty0) * ntx + (tx - tx0));
+        }
+        for (int f = tid; f < n * N; f += TS::NT) part[f] = 0.f;
+        __syncthreads();
+        if (any) {
+            int idx[TS::PPT];
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                float t = 0.f;
+            for (int k = 0; k < TS::PPT; ++k) idx[k] = -1;
+            for (int e = 0; e < n; ++e) {
+                const int t = ent[e];
 #pragma unroll
-                for (int q = 0; q < TS::NW; ++q) t += part[q][e][i];
-                dst[i] = t;
+                for (int k = 0; k < TS::PPT; ++k)
+                    if (key[k] == t) idx[k] = e;
             }
+#pragma unroll
+            for (int k = 0; k < TS::PPT; ++k) {
+                if (idx[k] < 0) continue;
+                matched[k] = true;
+                if (!act[k]) continue;
+                float *row = part + idx[k] * N;
+#pragma unroll
+                for (int i = 0; i < N; ++i)
+                    if (val[k][i] != 0.f) atomicAdd(row + i, val[k][i]);
+            }
+            __syncthreads();
+        }
+        for (int f = tid; f < n * N; f += TS::NT) {
+            const int e = f / N, i = f - e * N;
+            pair_sums[(size_t)slot[e] * kNV + i] = part[f];
         }
         __syncthreads();
     }
@@ -597,7 +607,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             block_sum_store<TS::NW>(accl[q], part_render + R.part_off + ((long long)q * ntiles + lt) * 22);
         }
     }
-    tile_pair_sums<T, kNV>(cv, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, matched, pair_sums);
+    tile_pair_sums<T, kNV>(cv, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, act, matched, pair_sums);
     overflow_rows(cv, key, val, act, matched, gtri);
 }
 
@@ -606,7 +616,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
 template <int T>
 __global__ __launch_bounds__(256) void light_backward_kernel(
     const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup, const int *__restrict__ faces,
-    const int *__restrict__ adj, const float *__restrict__ verts, const float4 *__restrict__ clip,
+    const unsigned char *__restrict__ silm, const float *__restrict__ verts, const float4 *__restrict__ clip,
     const unsigned long long *__restrict__ keys, const float *__restrict__ F0, const float *__restrict__ gF1,
     float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ pair_off, float *__restrict__ pair_sums, float *__restrict__ gtri,
@@ -650,7 +660,7 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
                 if ((unsigned)kn == (unsigned)ks) continue;
                 bool self_front;
                 AAPair pr;
-                if (!aa_eval<true>(l, setup, faces, adj, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
+                if (!aa_eval<true>(l, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
                 const bool self_recv = (pr.recv == 1) != self_front;
                 if (self_recv) {
                     g0 -= pr.w * gs0;
@@ -718,7 +728,7 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
         }
     }
     block_sum_store<TS::NW>(accl, part_light + ((long long)l.part_off + lt) * 6);
-    tile_pair_sums<T, 18>(l, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, matched, pair_sums);
+    tile_pair_sums<T, 18>(l, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, act, matched, pair_sums);
     overflow_rows(l, key, val, act, matched, gtri);
 }
 
@@ -995,12 +1005,12 @@ __global__ __launch_bounds__(256) void pose_backward_kernel(const int *__restric
 // ----------------------------------------------------------------------------- launchers
 
 hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
-                                     const TriSetup *setup, const int *faces, const int *adj, const float *verts,
+                                     const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
                                      const unsigned long long *keys, const float *img0, const float *gimg,
                                      float *gimg0, float4 *gclip, int C, hipStream_t s) {
     if (R == 0) return hipSuccess;
     hipLaunchKernelGGL(aa_camera_backward_kernel, dim3((max_pix + 255) / 256, R), dim3(256), 0, s, views, renders,
-                       setup, faces, adj, verts, keys, img0, gimg, gimg0, gclip, C);
+                       setup, faces, silm, verts, keys, img0, gimg, gimg0, gclip, C);
     return hipGetLastError();
 }
 
@@ -1030,14 +1040,14 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
 }
 
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
-                                 const int *faces, const int *adj, const float *verts, const float4 *clip,
+                                 const int *faces, const unsigned char *silm, const float *verts, const float4 *clip,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *pair_off,
                                  float *pair_sums, float *gtri, float *part_light, hipStream_t s) {
     if (L == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, L);
 #define DSM_LIB(TT)                                                                                                  \
-    hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, adj,   \
+    hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, silm,  \
                        verts, clip, keys, F0, gF1, gclip, tile_start, bins, pair_off, pair_sums, gtri, part_light)
     if (tile == 8) DSM_LIB(8);
     else if (tile == 16) DSM_LIB(16);

@@ -163,12 +163,15 @@ __global__ void setup_kernel(const ViewConst *__restrict__ views, const int *__r
 // no triangle or more than one other triangle shares it, or when the
 // neighbour across it faces the other way in this view.
 __global__ void silhouette_kernel(const ViewConst *__restrict__ views, const int *__restrict__ adj,
-                                  TriSetup *__restrict__ setup) {
+                                  TriSetup *__restrict__ setup, unsigned char *__restrict__ silm) {
     const ViewConst &v = views[blockIdx.y];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= v.nfaces) return;
     TriSetup &s = setup[v.setup_off + t];
-    if (s.facing == 0) return;
+    if (s.facing == 0) {
+        silm[v.setup_off + t] = 0;
+        return;
+    }
     const bool sw = s.swapped != 0;
     unsigned mask = 0;
     for (int e = 0; e < 3; ++e) {
@@ -178,6 +181,7 @@ __global__ void silhouette_kernel(const ViewConst *__restrict__ views, const int
         if (nb < 0 || setup[v.setup_off + nb].facing != s.facing) mask |= 1u << e;
     }
     s.sil = (unsigned char)mask;
+    silm[v.setup_off + t] = (unsigned char)mask;   // compact copy for the edge-smoothing passes
 }
 
 // ----------------------------------------------------------------------------- scan (exclusive, uint32)
@@ -472,9 +476,9 @@ hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, c
 }
 
 hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj, TriSetup *setup,
-                              hipStream_t s) {
+                              unsigned char *silm, hipStream_t s) {
     if (nviews == 0 || max_faces == 0) return hipSuccess;
-    hipLaunchKernelGGL(silhouette_kernel, dim3((max_faces + 255) / 256, nviews), dim3(256), 0, s, views, adj, setup);
+    hipLaunchKernelGGL(silhouette_kernel, dim3((max_faces + 255) / 256, nviews), dim3(256), 0, s, views, adj, setup, silm);
     return hipGetLastError();
 }
 

@@ -89,7 +89,7 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const int *_
 template <bool LIGHT>
 __global__ void aa_forward_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
                                   const TriSetup *__restrict__ setup, const int *__restrict__ faces,
-                                  const int *__restrict__ adj, const float *__restrict__ verts,
+                                  const unsigned char *__restrict__ silm, const float *__restrict__ verts,
                                   const unsigned long long *__restrict__ keys, const float *__restrict__ src,
                                   float *__restrict__ dst, int C) {
     const ViewConst &v = LIGHT ? views[blockIdx.y] : views[renders[blockIdx.y].camera_view];
@@ -115,7 +115,7 @@ __global__ void aa_forward_kernel(const ViewConst *__restrict__ views, const Ren
             if ((unsigned)kn == (unsigned)ks) continue;
             bool self_front;
             AAPair pr;
-            if (!aa_eval<false>(v, setup, faces, adj, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
+            if (!aa_eval<false>(v, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
             const bool self_recv = (pr.recv == 1) != self_front;   // receiver: other when recv==1
             if (!self_recv) continue;
             for (int c = 0; c < C; ++c) {
@@ -247,15 +247,15 @@ hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const i
 }
 
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
-                             const TriSetup *setup, const int *faces, const int *adj, const float *verts,
+                             const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
                              const unsigned long long *keys, const float *src, float *dst, int C, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const dim3 grid((max_pix + 255) / 256, n);
     if (light)
-        hipLaunchKernelGGL(aa_forward_kernel<true>, grid, dim3(256), 0, s, views, renders, setup, faces, adj, verts,
+        hipLaunchKernelGGL(aa_forward_kernel<true>, grid, dim3(256), 0, s, views, renders, setup, faces, silm, verts,
                            keys, src, dst, 2);
     else
-        hipLaunchKernelGGL(aa_forward_kernel<false>, grid, dim3(256), 0, s, views, renders, setup, faces, adj, verts,
+        hipLaunchKernelGGL(aa_forward_kernel<false>, grid, dim3(256), 0, s, views, renders, setup, faces, silm, verts,
                            keys, src, dst, C);
     return hipGetLastError();
 }

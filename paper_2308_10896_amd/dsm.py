@@ -13,6 +13,10 @@ import torch
 
 from . import _lib
 
+# pipeline stages in launch order (the dsm_stage enum of the C ABI)
+STAGES = ('setup', 'bin', 'raster', 'resolve', 'light_aa', 'filter', 'lookup', 'camera_aa', 'bwd_setup',
+          'camera_aa_adj', 'lookup_adj', 'filter_adj', 'light_adj', 'vertex_grad', 'light_grad')
+
 __all__ = ['filter_moments', 'version']
 
 
@@ -235,6 +239,18 @@ class Plan:
 
     def graph_launch(self, stream):
         _lib.call('dsm_graph_launch', self.handle, C.c_void_p(stream.cuda_stream))
+
+    def time_stages(self, stream, verts, light_params, albedo, saved, scratch, images, grad_images, grad_verts,
+                    grad_light_params, grad_albedo, reps):
+        """Mean duration (ms) of every pipeline stage over `reps` eager
+        forward + backward passes on `stream`, timed with HIP events."""
+        ms = (C.c_float * len(STAGES))()
+        with torch.cuda.stream(stream):
+            _lib.call('dsm_time_stages', self.handle, _ptr(verts), _ptr(light_params), _ptr(albedo), _ptr(saved),
+                      saved.numel(), _ptr(scratch), scratch.numel(), _ptr(images), _ptr(grad_images),
+                      _ptr(grad_verts), _ptr(grad_light_params), _ptr(grad_albedo), int(reps), ms,
+                      C.c_void_p(stream.cuda_stream))
+        return dict(zip(STAGES, (float(x) for x in ms)))
 
 
 class _Render(torch.autograd.Function):

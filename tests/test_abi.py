@@ -6,6 +6,8 @@ import re
 
 import pytest
 
+from paper_2308_10896_amd import dsm
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -46,3 +48,11 @@ def test_filter_validation_on_host():
     assert lib.dsm_filter_moments(64, 1, 0, 5, 0.0, None, 2, 0, None) == 1
     # zero maps is a no-op
     assert lib.dsm_filter_moments(64, 0, 0, 5, 0.0, None, None, 0, None) == 0
+
+
+def test_stage_names_follow_header_enum():
+    text = open(os.path.join(ROOT, 'include', 'dsm.h')).read()
+    body = text[text.index('DSM_STAGE_SETUP = 0'):text.index('} dsm_stage;')]
+    names = re.findall(r'DSM_STAGE_([A-Z_]+)', body)
+    assert names[-1] == 'COUNT'
+    assert tuple(n.lower() for n in names[:-1]) == dsm.STAGES
