@@ -311,6 +311,8 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
     p->sc_tile_start = o; o = align_up(o + 4 * ((size_t)tiles + 1));
     p->sc_bins = o; o = align_up(o + 4 * (size_t)p->capacity);
+    p->sc_bin_pair = o; o = align_up(o + 4 * (size_t)p->capacity);
+    p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
     p->sc_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_F1 = o; o = align_up(o + 4 * (size_t)maps);
     p->sc_gimg0 = o; o = align_up(o + 4 * (size_t)img);
@@ -455,6 +457,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     unsigned *scan = at<unsigned>(scratch, p->sc_scan);
     unsigned *tile_start = at<unsigned>(scratch, p->sc_tile_start);
     unsigned *bins = at<unsigned>(scratch, p->sc_bins);
+    unsigned *bin_pair = at<unsigned>(scratch, p->sc_bin_pair);
     unsigned *overflow = at<unsigned>(scratch, p->sc_overflow);
     float *F1 = at<float>(scratch, p->sc_F1);
     unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
@@ -474,7 +477,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_MARK(DSM_STAGE_BIN);
     DSM_TRY(launch_scan(pair_cnt, pair_off, scan, p->ntri, s));
     DSM_TRY(launch_binning(p->views_d, setup, pair_off, p->ntri, p->capacity, p->tile, tile_cnt, tile_start,
-                           tile_cursor, scan, p->ntiles, bins, overflow, cnt, s));
+                           tile_cursor, scan, p->ntiles, bins, bin_pair, overflow, cnt, s));
     DSM_MARK(DSM_STAGE_RASTER);
     DSM_TRY(launch_raster(p->views_d, p->tile_view_d, p->ntiles, p->tile, setup, tile_start, bins, overflow, cnt, cnt,
                           keys, s));
@@ -509,6 +512,8 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     const unsigned *pair_off = at<unsigned>(scratch, p->sc_pair_off);
     const unsigned *tile_start = at<unsigned>(scratch, p->sc_tile_start);
     const unsigned *bins = at<unsigned>(scratch, p->sc_bins);
+    const unsigned *bin_pair = at<unsigned>(scratch, p->sc_bin_pair);
+    unsigned char *pair_flag = at<unsigned char>(scratch, p->sc_pair_flag);
     const unsigned *overflow = at<unsigned>(scratch, p->sc_overflow);
     float *gimg0 = at<float>(scratch, p->sc_gimg0);
     unsigned *big_count = at<unsigned>(scratch, p->sc_bigcount);
@@ -534,18 +539,20 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_TRY(launch_lookup_backward(p->tile, p->views_d, p->L, p->Cm, p->max_cam_tiles, p->max_lights_per_render,
                                    p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
                                    p->faces_d, verts, albedo, clip, keys, Mm, gimg0, gM, setup, tile_start, bins,
-                                   pair_off, pair_sums, gtri, part_render, p->C, s));
+                                   bin_pair, pair_flag, pair_sums, gtri, part_render, p->C, s));
     DSM_MARK(DSM_STAGE_FILTER_ADJ);
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
     DSM_MARK(DSM_STAGE_LIGHT_ADJ);
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
-                                  clip, keys, F0, gF1, gclip, tile_start, bins, pair_off, pair_sums, gtri, part_light,
+                                  clip, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,
+                                  part_light,
                                   s));
     DSM_MARK(DSM_STAGE_VERTEX_GRAD);
     DSM_TRY(launch_vertex_gradients(p->views_d, p->L, p->B, p->max_scene_verts, p->max_scene_faces, p->ntri,
                                     p->capacity, p->scene_vert_off_d, p->scene_face_off_d, p->scene_views_off_d,
-                                    p->scene_views_d, p->vc_off_d, p->vc_list_d, pair_off, pair_sums, gtri, big_list,
+                                    p->scene_views_d, p->vc_off_d, p->vc_list_d, pair_off, pair_flag, pair_sums, gtri,
+                                    big_list,
                                     big_count, verts, gclip, gverts, part_gm, galbedo, p->C, s));
     DSM_MARK(DSM_STAGE_LIGHT_GRAD);
     DSM_TRY(launch_glight_reduce(p->views_d, p->L, p->renders_d, p->light_renders_off_d, p->light_renders_d, part_gm,

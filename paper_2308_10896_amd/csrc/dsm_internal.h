@@ -154,7 +154,7 @@ hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int
 hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,
                           unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
                           unsigned *tile_cursor, unsigned *scan_scratch, int ntiles, unsigned *bins,
-                          unsigned *overflow_list, DevCounters *counters, hipStream_t s);
+                          unsigned *bin_pair, unsigned *overflow_list, DevCounters *counters, hipStream_t s);
 hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntiles, int tile, const TriSetup *setup,
                          const unsigned *tile_start, const unsigned *bins, const unsigned *overflow_list,
                          const DevCounters *counters_ro, DevCounters *counters, unsigned long long *keys,
@@ -178,17 +178,19 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const int *render_lights, const int *faces, const float *verts, const float *albedo,
                                   const float4 *clip, const unsigned long long *keys, const float *maps,
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
-                                  const unsigned *bins, const unsigned *pair_off, float *pair_sums, float *gtri,
-                                  float *part_render, int C, hipStream_t s);
+                                  const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
+                                  float *pair_sums, float *gtri, float *part_render, int C, hipStream_t s);
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const unsigned char *silm, const float *verts, const float4 *clip,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
-                                 const unsigned *tile_start, const unsigned *bins, const unsigned *pair_off,
-                                 float *pair_sums, float *gtri, float *part_light, hipStream_t s);
+                                 const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
+                                 unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
+                                 hipStream_t s);
 hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max_verts, int max_faces, int ntri,
                                    unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
                                    const int *scene_views_off, const int *scene_views, const int *vc_off,
-                                   const int *vc_list, const unsigned *pair_off, const float *pair_sums, float *gtri,
+                                   const int *vc_list, const unsigned *pair_off, const unsigned char *pair_flag,
+                                   const float *pair_sums, float *gtri,
                                    unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
                                    float *gverts, float *part_gm, float *galbedo, int C, hipStream_t s);
 hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *counters, float *gtri, hipStream_t s);

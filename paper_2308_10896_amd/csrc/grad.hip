@@ -196,25 +196,29 @@ __device__ __forceinline__ void block_sum_store(const float (&val)[N], float *ds
 // pixels it owns -> pair_sums[pair index][0..N), zeros when it owns none.
 // Marks the pixels whose triangle was found.  Uniform call.
 //
-// The bin is walked in chunks of 64 entries.  Each pixel finds the entry of
-// its triangle (a broadcast LDS scan of the chunk) and adds its N values
-// into that entry's LDS row with LDS atomics; the rows are then stored
-// contiguously.  Cost per pixel is N LDS adds however many triangles share
-// the tile, so dense meshes (about one triangle per pixel) stay cheap.
+// The bin is walked in chunks of 64 entries (triangle and pair index, both
+// written by the binning pass).  Each pixel finds the entry of its triangle
+// (a broadcast LDS scan of the chunk) and adds its N values into that
+// entry's LDS row with LDS atomics.  Every entry's pair_flag byte is written
+// (1: the row holds a sum, 0: the triangle owns no active pixel here), and
+// only flagged rows are stored.  Cost per pixel is N LDS adds however many
+// triangles share the tile, so dense meshes (about one triangle per pixel)
+// stay cheap.
 template <int T, int N>
-__device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, int tx, int ty,
-                                               const TriSetup *__restrict__ setup,
-                                               const unsigned *__restrict__ tile_start,
-                                               const unsigned *__restrict__ bins, const unsigned *__restrict__ pair_off,
+__device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, const unsigned *__restrict__ tile_start,
+                                               const unsigned *__restrict__ bins,
+                                               const unsigned *__restrict__ bin_pair,
                                                const int (&key)[TileShape<T>::PPT],
                                                const float (&val)[TileShape<T>::PPT][N],
                                                const bool (&act)[TileShape<T>::PPT],
-                                               bool (&matched)[TileShape<T>::PPT], float *__restrict__ pair_sums) {
+                                               bool (&matched)[TileShape<T>::PPT],
+                                               unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums) {
     using TS = TileShape<T>;
     constexpr int CH = 64;
     __shared__ float part[CH * N];
     __shared__ int ent[CH];
     __shared__ unsigned slot[CH];
+    __shared__ int hit[CH];
     const int tid = threadIdx.x;
     const unsigned b0 = tile_start[gt], b1 = tile_start[gt + 1];
     bool mine = false;
@@ -224,13 +228,12 @@ __device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, int t
     for (unsigned c0 = b0; c0 < b1; c0 += CH) {
         const int n = (int)min((unsigned)CH, b1 - c0);
         if (tid < n) {
-            const unsigned si = bins[c0 + tid];
-            ent[tid] = (int)(si - (unsigned)v.setup_off);
-            const TriSetup &st = setup[si];
-            const int tx0 = st.bx0 / T, ty0 = st.by0 / T, ntx = st.bx1 / T - tx0 + 1;
-            slot[tid] = pair_off[si] + (unsigned)((ty - ty0) * ntx + (tx - tx0));
+            ent[tid] = (int)(bins[c0 + tid] - (unsigned)v.setup_off);
+            slot[tid] = bin_pair[c0 + tid];
+            hit[tid] = 0;
         }
-        for (int f = tid; f < n * N; f += TS::NT) part[f] = 0.f;
+        if (any)
+            for (int f = tid; f < n * N; f += TS::NT) part[f] = 0.f;
         __syncthreads();
         if (any) {
             int idx[TS::PPT];
@@ -247,6 +250,7 @@ __device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, int t
                 if (idx[k] < 0) continue;
                 matched[k] = true;
                 if (!act[k]) continue;
+                hit[idx[k]] = 1;
                 float *row = part + idx[k] * N;
 #pragma unroll
                 for (int i = 0; i < N; ++i)
@@ -254,10 +258,12 @@ __device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, int t
             }
             __syncthreads();
         }
-        for (int f = tid; f < n * N; f += TS::NT) {
-            const int e = f / N, i = f - e * N;
-            pair_sums[(size_t)slot[e] * kNV + i] = part[f];
-        }
+        if (tid < n) pair_flag[slot[tid]] = (unsigned char)hit[tid];
+        if (any)
+            for (int f = tid; f < n * N; f += TS::NT) {
+                const int e = f / N, i = f - e * N;
+                if (hit[e]) pair_sums[(size_t)slot[e] * kNV + i] = part[f];
+            }
         __syncthreads();
     }
 }
@@ -537,8 +543,8 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     const float *__restrict__ albedo, const float4 *__restrict__ clip, const unsigned long long *__restrict__ keys,
     const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
     const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
-    const unsigned *__restrict__ pair_off, float *__restrict__ pair_sums, float *__restrict__ gtri,
-    float *__restrict__ part_render, int C) {
+    const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
+    float *__restrict__ gtri, float *__restrict__ part_render, int C) {
     using TS = TileShape<T>;
     const int cam = blockIdx.y;
     const ViewConst &cv = views[L + cam];
@@ -607,7 +613,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             block_sum_store<TS::NW>(accl[q], part_render + R.part_off + ((long long)q * ntiles + lt) * 22);
         }
     }
-    tile_pair_sums<T, kNV>(cv, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, act, matched, pair_sums);
+    tile_pair_sums<T, kNV>(cv, gt, tile_start, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(cv, key, val, act, matched, gtri);
 }
 
@@ -619,8 +625,8 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
     const unsigned char *__restrict__ silm, const float *__restrict__ verts, const float4 *__restrict__ clip,
     const unsigned long long *__restrict__ keys, const float *__restrict__ F0, const float *__restrict__ gF1,
     float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
-    const unsigned *__restrict__ pair_off, float *__restrict__ pair_sums, float *__restrict__ gtri,
-    float *__restrict__ part_light) {
+    const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
+    float *__restrict__ gtri, float *__restrict__ part_light) {
     using TS = TileShape<T>;
     const int lidx = blockIdx.y;
     const ViewConst &l = views[lidx];
@@ -728,7 +734,7 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
         }
     }
     block_sum_store<TS::NW>(accl, part_light + ((long long)l.part_off + lt) * 6);
-    tile_pair_sums<T, 18>(l, gt, tx, ty, setup, tile_start, bins, pair_off, key, val, act, matched, pair_sums);
+    tile_pair_sums<T, 18>(l, gt, tile_start, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(l, key, val, act, matched, gtri);
 }
 
@@ -747,6 +753,7 @@ constexpr unsigned kBigPairs = 16;
 
 // gtri[i] = sum of triangle i's pair slots (triangles with many pairs are listed for the big pass).
 __global__ void pair_reduce_kernel(const unsigned *__restrict__ pair_off, int ntri, unsigned capacity,
+                                   const unsigned char *__restrict__ pair_flag,
                                    const float *__restrict__ pair_sums, float *__restrict__ gtri,
                                    unsigned *__restrict__ big_list, unsigned *__restrict__ big_count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -761,13 +768,15 @@ __global__ void pair_reduce_kernel(const unsigned *__restrict__ pair_off, int nt
 #pragma unroll
     for (int q = 0; q < kNV; ++q) acc[q] = 0.f;
     for (unsigned p = a; p < b; ++p)
+        if (pair_flag[p])
 #pragma unroll
-        for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
+            for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
 #pragma unroll
     for (int q = 0; q < kNV; ++q) gtri[(size_t)i * kNV + q] = acc[q];
 }
 
 __global__ __launch_bounds__(256) void big_pair_reduce_kernel(const unsigned *__restrict__ pair_off,
+                                                              const unsigned char *__restrict__ pair_flag,
                                                               const float *__restrict__ pair_sums,
                                                               float *__restrict__ gtri,
                                                               const unsigned *__restrict__ big_list,
@@ -780,8 +789,9 @@ __global__ __launch_bounds__(256) void big_pair_reduce_kernel(const unsigned *__
 #pragma unroll
         for (int q = 0; q < kNV; ++q) acc[q] = 0.f;
         for (unsigned p = a + threadIdx.x; p < b; p += blockDim.x)
+            if (pair_flag[p])
 #pragma unroll
-            for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
+                for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
         block_sum_store<4>(acc, gtri + (size_t)i * kNV);
         __syncthreads();
     }
@@ -1019,14 +1029,14 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const int *render_lights, const int *faces, const float *verts, const float *albedo,
                                   const float4 *clip, const unsigned long long *keys, const float *maps,
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
-                                  const unsigned *bins, const unsigned *pair_off, float *pair_sums, float *gtri,
-                                  float *part_render, int C, hipStream_t s) {
+                                  const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
+                                  float *pair_sums, float *gtri, float *part_render, int C, hipStream_t s) {
     if (Cm == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, Cm);
 #define DSM_LB(TT, ML)                                                                                              \
     hipLaunchKernelGGL((lookup_backward_kernel<TT, ML>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,   \
                        cam_renders_off, cam_renders, render_lights, faces, verts, albedo, clip, keys, maps, gimg0,   \
-                       gmaps, setup, tile_start, bins, pair_off, pair_sums, gtri, part_render, C)
+                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C)
 #define DSM_LB_T(TT)                                                  \
     if (max_lights <= 1) DSM_LB(TT, 1);                               \
     else if (max_lights <= 4) DSM_LB(TT, 4);                          \
@@ -1042,13 +1052,15 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const unsigned char *silm, const float *verts, const float4 *clip,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
-                                 const unsigned *tile_start, const unsigned *bins, const unsigned *pair_off,
-                                 float *pair_sums, float *gtri, float *part_light, hipStream_t s) {
+                                 const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
+                                 unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
+                                 hipStream_t s) {
     if (L == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, L);
 #define DSM_LIB(TT)                                                                                                  \
     hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, silm,  \
-                       verts, clip, keys, F0, gF1, gclip, tile_start, bins, pair_off, pair_sums, gtri, part_light)
+                       verts, clip, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,   \
+                       part_light)
     if (tile == 8) DSM_LIB(8);
     else if (tile == 16) DSM_LIB(16);
     else DSM_LIB(32);
@@ -1059,13 +1071,15 @@ hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int ma
 hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max_verts, int max_faces, int ntri,
                                    unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
                                    const int *scene_views_off, const int *scene_views, const int *vc_off,
-                                   const int *vc_list, const unsigned *pair_off, const float *pair_sums, float *gtri,
+                                   const int *vc_list, const unsigned *pair_off, const unsigned char *pair_flag,
+                                   const float *pair_sums, float *gtri,
                                    unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
                                    float *gverts, float *part_gm, float *galbedo, int C, hipStream_t s) {
     if (ntri > 0) {
         hipLaunchKernelGGL(pair_reduce_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
-                           pair_sums, gtri, big_list, big_count);
-        hipLaunchKernelGGL(big_pair_reduce_kernel, dim3(512), dim3(256), 0, s, pair_off, pair_sums, gtri, big_list,
+                           pair_flag, pair_sums, gtri, big_list, big_count);
+        hipLaunchKernelGGL(big_pair_reduce_kernel, dim3(512), dim3(256), 0, s, pair_off, pair_flag, pair_sums, gtri,
+                           big_list,
                            (const unsigned *)big_count);
     }
     if (max_verts > 0)

@@ -290,7 +290,7 @@ template <bool FILL>
 __global__ void bin_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
                            const unsigned *__restrict__ pair_off, int ntri, unsigned capacity, int tile,
                            unsigned *__restrict__ tile_count, const unsigned *__restrict__ tile_start,
-                           unsigned *__restrict__ bins) {
+                           unsigned *__restrict__ bins, unsigned *__restrict__ bin_pair) {
     const unsigned total = min(pair_off[ntri], capacity);
     for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
         const int i = find_tri(pair_off, ntri, p);
@@ -307,6 +307,7 @@ __global__ void bin_kernel(const ViewConst *__restrict__ views, const TriSetup *
         } else {
             const unsigned slot = atomicAdd(&tile_count[gt], 1u);
             bins[tile_start[gt] + slot] = (unsigned)i;
+            bin_pair[tile_start[gt] + slot] = p;
         }
     }
 }
@@ -493,15 +494,15 @@ hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const
 hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,
                           unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
                           unsigned *tile_cursor, unsigned *scan_scratch, int ntiles, unsigned *bins,
-                          unsigned *overflow_list, DevCounters *counters, hipStream_t s) {
+                          unsigned *bin_pair, unsigned *overflow_list, DevCounters *counters, hipStream_t s) {
     const int grid = 2048;
     hipLaunchKernelGGL(pairs_total_kernel, dim3(1), dim3(1), 0, s, pair_off, ntri, counters);
     hipLaunchKernelGGL(bin_kernel<false>, dim3(grid), dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
-                       tile_count, (const unsigned *)nullptr, (unsigned *)nullptr);
+                       tile_count, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr);
     hipError_t e = launch_scan(tile_count, tile_start, scan_scratch, ntiles, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bin_kernel<true>, dim3(grid), dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
-                       tile_cursor, (const unsigned *)tile_start, bins);
+                       tile_cursor, (const unsigned *)tile_start, bins, bin_pair);
     if (ntri > 0)
         hipLaunchKernelGGL(overflow_list_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
                            overflow_list, counters);
