@@ -42,7 +42,7 @@ def parse():
     ap.add_argument('--cpu-seconds', type=float, default=15.0,
                     help='time budget of the oracle baseline sample')
     ap.add_argument('--stage-reps', type=int, default=10)
-    ap.add_argument('--tile', type=int, default=0)
+    ap.add_argument('--tile', type=int, default=0, help='raster tile side; 0: autotune')
     return ap.parse_args()
 
 
@@ -74,14 +74,25 @@ def main():
     tris = [len(s.faces) for s in batch.scenes]
     stream = torch.cuda.Stream()
 
-    # ---------------- batched: one plan, one graph of pose+fwd+bwd+pose^T
-    plan = dsm.Plan(batch, tile_size=args.tile)
+    # ---------------- tile side and bin depth: given, or chosen by the autotuner
     local, lp, alb, poses = dsm.batch_inputs(batch, dev)
+    plan = dsm.Plan(batch)
+    rng = np.random.default_rng(0)
+    gimg = torch.as_tensor(rng.standard_normal(int(plan.info.image_floats)).astype(np.float32) * 1e-3, device=dev)
+    tune = None
+    if args.tile == 0:
+        with torch.cuda.stream(stream):
+            posed = plan.pose_forward(local, poses)
+            tile, scale, tune_ms = dsm.autotune(batch, posed, lp, alb, gimg, reps=3, stream=stream)
+        tune = {'tile': tile, 'bin_capacity_scale': scale, 'ms_fwd_bwd': round(tune_ms, 4)}
+    else:
+        tile, scale = args.tile, 0
+    del plan
+    # ---------------- batched: one plan, one graph of pose+fwd+bwd+pose^T
+    plan = dsm.Plan(batch, tile_size=tile, bin_capacity_scale=scale)
     saved, scratch = plan.workspace(dev)
     verts = torch.empty_like(local)
     images = torch.empty(int(plan.info.image_floats), device=dev)
-    rng = np.random.default_rng(0)
-    gimg = torch.as_tensor(rng.standard_normal(int(plan.info.image_floats)).astype(np.float32) * 1e-3, device=dev)
     gverts = torch.empty_like(local)
     glp = torch.empty_like(lp)
     galb = torch.empty_like(alb)
@@ -115,7 +126,7 @@ def main():
                           [sg.Light(**{**batch.lights[i].__dict__, 'scene': 0})],
                           [sg.Camera(**{**batch.cameras[i].__dict__, 'scene': 0})],
                           [sg.Render(0, [0])], channels=1)
-            p1 = dsm.Plan(b1, tile_size=args.tile)
+            p1 = dsm.Plan(b1, tile_size=tile, bin_capacity_scale=scale)
             l1, lp1, a1, po1 = dsm.batch_inputs(b1, dev)
             s1, sc1 = p1.workspace(dev)
             g1 = torch.as_tensor(rng.standard_normal(int(p1.info.image_floats)).astype(np.float32) * 1e-3, device=dev)
@@ -163,6 +174,8 @@ def main():
             'plain_renders_per_s': None if plain_rps is None else round(plain_rps, 2),
             'batched_over_plain': None if plain_rps is None else round(batched_rps / plain_rps, 3),
             'tile': int(plan.info.tile_size),
+            'bin_capacity_scale': int(plan.info.bin_capacity_scale),
+            'autotune': tune,
             'stages_us': kern['stages_us'],
         },
         'roofline': kern['roofline'],

@@ -162,7 +162,7 @@ const char *dsm_status_string(dsm_status status);
 /*
  * Build a plan for a batch: validates the description, uploads faces, builds
  * the edge adjacency used for silhouette tests, lays out every buffer.
- * tile_size: raster tile side (8, 16 or 32; 0 = library default 16);
+ * tile_size: raster tile side (8, 16 or 32; 0 = library default 8);
  * bin_capacity_scale: the tile bins hold bin_capacity_scale * (triangles +
  * tiles) / 4 (triangle, tile) pairs over all views (1..1024; 0 = default 32).
  * Triangles whose pairs do not fit are rasterized by a slower overflow path
@@ -297,6 +297,30 @@ dsm_status dsm_time_stages(dsm_plan *plan, const float *verts_dev, const float *
                            size_t scratch_bytes, float *images_dev, const float *grad_images_dev,
                            float *grad_verts_dev, float *grad_light_params_dev, float *grad_albedo_dev,
                            int32_t reps, float *ms_out, dsm_stream stream);
+
+/*
+ * Autotuner for the plan's tile side and bin depth (dsm_plan_create's
+ * tile_size and bin_capacity_scale).  For every candidate (tile side 8, 16,
+ * 32; bin capacity scale 8, 32) it builds a plan for `desc`, runs one
+ * untimed and `reps` timed dsm_forward + dsm_backward passes on the given
+ * inputs (same layouts as there; grad_images_dev has the plan's
+ * image_floats) on `stream`, and returns the fastest choice in
+ * *tile_size_out / *bin_capacity_scale_out and its mean milliseconds per
+ * forward + backward in *ms_out (nullable).  The device work is timed with
+ * HIP events; the call waits for `stream` and allocates and frees its own
+ * device buffers.  cache_path (nullable) names a text file of earlier
+ * decisions, one "key tile scale ms" line each, keyed by a hash of the
+ * batch's shape (counts, mesh sizes, map and image sizes, filters) and the
+ * device: a hit returns the stored choice without timing, a miss appends the
+ * new one.  Errors: DSM_ERR_INVALID_ARG for null required pointers or reps
+ * outside [1, DSM_MAX_TIMING_REPS], or a description dsm_plan_create
+ * rejects; DSM_ERR_NO_DEVICE without a device; DSM_ERR_OUT_OF_MEMORY when
+ * no candidate fits in device memory; DSM_ERR_HIP on a failed HIP call.
+ */
+dsm_status dsm_autotune(const dsm_batch_desc *desc, const float *verts_dev, const float *light_params_dev,
+                        const float *albedo_dev, const float *grad_images_dev, int32_t reps,
+                        const char *cache_path, dsm_stream stream, int32_t *tile_size_out,
+                        int32_t *bin_capacity_scale_out, float *ms_out);
 
 #ifdef __cplusplus
 }

@@ -87,6 +87,8 @@ _SIGNATURES = {
     'dsm_get_render_image0': (C.c_int, [P, P, I32, P, P]),
     'dsm_get_stats': (C.c_int, [P, P, C.POINTER(Stats), P]),
     'dsm_filter_moments': (C.c_int, [I32, I32, I32, I32, F32, P, P, I32, P]),
+    'dsm_autotune': (C.c_int, [C.POINTER(BatchDesc), P, P, P, P, I32, C.c_char_p, P, C.POINTER(I32),
+                               C.POINTER(I32), C.POINTER(C.c_float)]),
     'dsm_time_stages': (C.c_int, [P, P, P, P, P, SZ, P, SZ, P, P, P, P, P, I32, C.POINTER(C.c_float), P]),
 }
 

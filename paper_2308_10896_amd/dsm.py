@@ -59,14 +59,10 @@ def _cptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
-class Plan:
-    """A batch of scenes / lights / cameras / renders bound to the HIP library.
+class _BatchDesc:
+    """Host-side dsm_batch_desc of a batch, with the arrays it points to."""
 
-    ``batch`` follows the layout of ``scenegen.Batch`` (any object with the
-    same attributes works).  The plan owns device copies of faces and
-    adjacency; vertices, light parameters and albedo are passed per call."""
-
-    def __init__(self, batch, tile_size: int = 0, bin_capacity_scale: int = 0):
+    def __init__(self, batch):
         L = _lib
         scenes = batch.scenes
         self.num_scenes = len(scenes)
@@ -134,6 +130,23 @@ class Plan:
         desc.render_light_list = _cptr(self.render_light_list, C.c_int32)
         desc.channels = self.channels
         desc.camera_antialias = int(getattr(batch, 'antialias_camera', True))
+        self.desc = desc
+
+
+class Plan:
+    """A batch of scenes / lights / cameras / renders bound to the HIP library.
+
+    ``batch`` follows the layout of ``scenegen.Batch`` (any object with the
+    same attributes works).  The plan owns device copies of faces and
+    adjacency; vertices, light parameters and albedo are passed per call."""
+
+    def __init__(self, batch, tile_size: int = 0, bin_capacity_scale: int = 0):
+        L = _lib
+        bd = _BatchDesc(batch)
+        self._desc = bd
+        desc = bd.desc
+        self.num_scenes = bd.num_scenes
+        self.channels = bd.channels
         h = C.c_void_p()
         L.call('dsm_plan_create', C.byref(desc), int(tile_size), int(bin_capacity_scale), C.byref(h))
         self.handle = h
@@ -251,6 +264,25 @@ class Plan:
                       _ptr(grad_verts), _ptr(grad_light_params), _ptr(grad_albedo), int(reps), ms,
                       C.c_void_p(stream.cuda_stream))
         return dict(zip(STAGES, (float(x) for x in ms)))
+
+
+def autotune(batch, verts, light_params, albedo, grad_images, reps: int = 3, cache_path: str | None = None,
+             stream=None):
+    """Pick the plan's (tile_size, bin_capacity_scale) by timing forward +
+    backward for every candidate on these inputs (dsm_autotune).  Returns
+    (tile_size, bin_capacity_scale, ms per forward + backward)."""
+    for name, t in (('verts', verts), ('light_params', light_params), ('albedo', albedo),
+                    ('grad_images', grad_images)):
+        _need_cuda_f32(name, t)
+    bd = _BatchDesc(batch)
+    tile = C.c_int32()
+    scale = C.c_int32()
+    ms = C.c_float()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    path = cache_path.encode() if cache_path else None
+    _lib.call('dsm_autotune', C.byref(bd.desc), _ptr(verts), _ptr(light_params), _ptr(albedo), _ptr(grad_images),
+              int(reps), path, C.c_void_p(st.cuda_stream), C.byref(tile), C.byref(scale), C.byref(ms))
+    return int(tile.value), int(scale.value), float(ms.value)
 
 
 class _Render(torch.autograd.Function):

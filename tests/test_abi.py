@@ -56,3 +56,22 @@ def test_stage_names_follow_header_enum():
     names = re.findall(r'DSM_STAGE_([A-Z_]+)', body)
     assert names[-1] == 'COUNT'
     assert tuple(n.lower() for n in names[:-1]) == dsm.STAGES
+
+
+def test_autotune_validation_on_host():
+    import ctypes as C
+    import scenegen as sg
+    from paper_2308_10896_amd import _lib
+    lib = _lib.lib()
+    t, s, ms = C.c_int32(), C.c_int32(), C.c_float()
+    # null description / outputs, bad repetition count: rejected before any device call
+    assert lib.dsm_autotune(None, None, None, None, None, 1, None, None, C.byref(t), C.byref(s), None) == 1
+    bd = dsm._BatchDesc(sg.config0())
+    assert lib.dsm_autotune(C.byref(bd.desc), None, None, None, None, 1, None, None, None, C.byref(s), None) == 1
+    assert lib.dsm_autotune(C.byref(bd.desc), None, None, None, None, 0, None, None, C.byref(t), C.byref(s),
+                            None) == 1
+    # a valid request on a host without a GPU
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.dsm_autotune(C.byref(bd.desc), None, None, None, None, 1, None, None, C.byref(t), C.byref(s),
+                                C.byref(ms)) == 5
