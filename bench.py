@@ -29,6 +29,42 @@ sys.path.insert(0, ROOT)
 METRIC = "shadowed fwd+bwd renders/sec at 512² (batched vs plain, 1 MI355X); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic per launch of the targeted kernels on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this
+# script (profiles/cfg2_hbm_traffic_pmc.md).  Each counter is scaled by what
+# it reads for a plain 128 MiB device-to-device copy in the same runs
+# (FETCH_SIZE reads 65550.4 KiB and WRITE_SIZE 131072 KiB for 131072 KiB
+# moved each way).  A record is only used while the kernel's sources hash to
+# the value they had when the counters were taken.
+PMC_FETCH_SCALE = 131072.0 / 65550.4
+PMC_WRITE_SCALE = 131072.0 / 131072.0
+PMC_TRAFFIC = {
+    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65824.9, write_kib=131072.0,
+                   sources=('blur.hip', 'dsm_internal.h'), sha1='81724dd5bf71c42b'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65697.8, write_kib=131072.0,
+                       sources=('blur.hip', 'dsm_internal.h'), sha1='81724dd5bf71c42b'),
+    'lookup': dict(kernel='lookup_kernel', fetch_kib=153613.3, write_kib=65536.0,
+                   sources=('shade.hip', 'dsm_internal.h'), sha1='2302679008d0f815'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel<8, 1>', fetch_kib=351212.8, write_kib=129501.4,
+                       sources=('grad.hip', 'dsm_internal.h'), sha1='1aaa6eff6cc949ee'),
+}
+
+
+def pmc_traffic(stage, tile):
+    """HBM bytes per launch measured by the counters, or None when no record
+    matches the current kernel sources (and tile side 8 they were taken at)."""
+    import hashlib
+    rec = PMC_TRAFFIC.get(stage)
+    if rec is None or tile != 8:
+        return None
+    m = hashlib.sha1()
+    for f in rec['sources']:
+        with open(os.path.join(ROOT, 'paper_2308_10896_amd', 'csrc', f), 'rb') as fh:
+            m.update(fh.read())
+    if m.hexdigest()[:16] != rec['sha1']:
+        return None
+    return 1024.0 * (rec['fetch_kib'] * PMC_FETCH_SCALE + rec['write_kib'] * PMC_WRITE_SCALE)
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -217,10 +253,13 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
         'lookup_adj': float(R * P * (4 + 4 * C) + R * 16.0 * S * S + 12.0 * (F + V).sum() + 12.0 * V.sum()),
     }
     kernels = {}
+    tile = int(plan.info.tile_size)
     for name, b in algo.items():
         us = 1000.0 * stages[name]
+        tr = pmc_traffic(name, tile)
         kernels[name] = dict(us=round(us, 2), bytes=b, gbs=round(b / (us * 1e-6) / 1e9, 1),
-                             frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+                             frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                             traffic=None if tr is None else round(tr))
     reps = 20
     with torch.cuda.stream(stream):
         maps = torch.stack([plan.light_maps(saved, scratch, l, 1) for l in range(n)]).contiguous()
@@ -239,7 +278,7 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
     dom = max(kernels, key=lambda k: kernels[k]['us'])
     d = kernels[dom]
     roof = {'kernel': dom, 'bound': 'hbm', 'achieved': d['gbs'], 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
-            'frac': d['frac'], 'traffic': None,
+            'frac': d['frac'], 'traffic': d['traffic'],
             'kernels': kernels,
             'copy_gbs': round(copy_gbs, 1)}
     return {'stages_us': {k: round(1000.0 * v, 2) for k, v in stages.items()}, 'roofline': roof}

@@ -37,17 +37,6 @@ __device__ __forceinline__ int find_job(const BlurJob *jobs, int njobs, int tile
     return lo;
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin, and each XCD has its
-// own L2.  Renumber them so that each XCD takes a contiguous range of tiles:
-// neighbouring tiles, which re-read each other's halo, then share an L2.
-// The map is a bijection on [0, n), so any dispatch order stays correct.
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-    constexpr int kXcd = 8;
-    const int xcd = b % kXcd, idx = b / kXcd;
-    const int per = n / kXcd, rem = n % kXcd;
-    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
-
 // Staged tile geometry for radius R.  LDS row layout: [pad | halo R | 64
 // interior | halo R | pad] with the interior at column H4 = 4 ceil(R / 4), so
 // that it is written with 128-bit stores.

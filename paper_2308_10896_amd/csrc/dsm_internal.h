@@ -122,6 +122,27 @@ __device__ __forceinline__ int wave_min(int v) {
     return min(min(r0, r1), min(r2, r3));
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each
+// XCD has its own L2.  These renumber a grid so that each XCD takes a
+// contiguous range of work items: neighbouring tiles and rows, which share
+// cache lines and halos, then share an L2.  Both are bijections, so any
+// dispatch order stays correct.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    constexpr int kXcd = 8;
+    const int xcd = b % kXcd, idx = b / kXcd;
+    const int per = n / kXcd, rem = n % kXcd;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+struct Blk {
+    int x, y;
+};
+__device__ __forceinline__ Blk xcd_block2() {
+    const int gx = (int)gridDim.x;
+    const int lin = xcd_remap((int)blockIdx.x + (int)blockIdx.y * gx, gx * (int)gridDim.y);
+    return Blk{lin % gx, lin / gx};
+}
+
 __device__ __forceinline__ void atomic_add_f32(float *p, float v) {
     if (v != 0.0f) atomicAdd(p, v);
 }

@@ -98,10 +98,11 @@ __global__ __launch_bounds__(256) void aa_camera_backward_kernel(
     const int *__restrict__ faces, const unsigned char *__restrict__ silm, const float *__restrict__ verts,
     const unsigned long long *__restrict__ keys, const float *__restrict__ img0, const float *__restrict__ gimg,
     float *__restrict__ gimg0, float4 *__restrict__ gclip, int C) {
-    const RenderConst &R = renders[blockIdx.y];
+    const Blk blk = xcd_block2();
+    const RenderConst &R = renders[blk.y];
     const ViewConst &v = views[R.camera_view];
     const int W = v.W, H = v.H;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blk.x * blockDim.x + threadIdx.x;
     if (p >= W * H) return;
     const float *c0 = img0 + R.img_off;
     const float *g = gimg + R.img_off;
@@ -546,9 +547,10 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
     float *__restrict__ gtri, float *__restrict__ part_render, int C) {
     using TS = TileShape<T>;
-    const int cam = blockIdx.y;
+    const Blk blk = xcd_block2();
+    const int cam = blk.y;
     const ViewConst &cv = views[L + cam];
-    const int lt = blockIdx.x;
+    const int lt = blk.x;
     if (lt >= cv.tiles_x * cv.tiles_y) return;     // whole workgroup
     const int gt = cv.tile_off + lt;
     const int tx = lt % cv.tiles_x, ty = lt / cv.tiles_x;
@@ -628,11 +630,12 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
     float *__restrict__ gtri, float *__restrict__ part_light) {
     using TS = TileShape<T>;
-    const int lidx = blockIdx.y;
+    const Blk blk = xcd_block2();
+    const int lidx = blk.y;
     const ViewConst &l = views[lidx];
     const int S = l.W;
     const long long plane = (long long)S * S;
-    const int lt = blockIdx.x;
+    const int lt = blk.x;
     if (lt >= l.tiles_x * l.tiles_y) return;     // whole workgroup
     const int gt = l.tile_off + lt;
     const int tx = lt % l.tiles_x, ty = lt / l.tiles_x;

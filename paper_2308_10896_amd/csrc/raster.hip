@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_kernel(
     constexpr int NT = NPIX < kRasterThreads ? NPIX : kRasterThreads;
     constexpr int PPT = NPIX / NT;
     __shared__ RasterTri tris[NT];
-    const int gt = blockIdx.x;
+    const int gt = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int view = tile_view[gt];
     const ViewConst &v = views[view];
     const int lt = gt - v.tile_off;

@@ -92,11 +92,12 @@ __global__ void aa_forward_kernel(const ViewConst *__restrict__ views, const Ren
                                   const unsigned char *__restrict__ silm, const float *__restrict__ verts,
                                   const unsigned long long *__restrict__ keys, const float *__restrict__ src,
                                   float *__restrict__ dst, int C) {
-    const ViewConst &v = LIGHT ? views[blockIdx.y] : views[renders[blockIdx.y].camera_view];
+    const Blk blk = xcd_block2();
+    const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
     const int W = v.W, H = v.H;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blk.x * blockDim.x + threadIdx.x;
     if (p >= W * H) return;
-    const long long base = LIGHT ? v.map_off : renders[blockIdx.y].img_off;
+    const long long base = LIGHT ? v.map_off : renders[blk.y].img_off;
     const long long cstride = LIGHT ? (long long)W * H : 1;
     const int pstride = LIGHT ? 1 : C;
     const int i = p % W, j = p / W;

@@ -147,6 +147,11 @@ class Plan:
         desc = bd.desc
         self.num_scenes = bd.num_scenes
         self.channels = bd.channels
+        self.vert_offsets = bd.vert_offsets
+        self.face_offsets = bd.face_offsets
+        self.faces = bd.faces
+        self.pose_counts = bd.pose_counts
+        self.pose_centers = bd.pose_centers
         h = C.c_void_p()
         L.call('dsm_plan_create', C.byref(desc), int(tile_size), int(bin_capacity_scale), C.byref(h))
         self.handle = h
