@@ -260,7 +260,9 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         delete p;
         return DSM_ERR_INVALID_ARG;
     }
-    p->capacity = (unsigned)((long long)bin_capacity_scale * (tri + tiles) / 4);
+    // pair rows are addressed with 32-bit offsets (pair * 21 + value)
+    p->capacity = (unsigned)std::min<long long>((long long)bin_capacity_scale * (tri + tiles) / 4,
+                                                (long long)(0xFFFFFFFFu / 21u));
 
     // blur jobs over all light maps, grouped by filter radius (one launch per radius)
     {

@@ -107,6 +107,43 @@ __device__ __forceinline__ float wave_sum(float v) {
     return (r0 + r1) + (r2 + r3);
 }
 
+// Wave-wide sums of N <= 32 values at once by recursive halving: at each
+// butterfly step every lane keeps half of its remaining values and receives
+// its partner's copy of that half, so the 64 lanes end up each holding one
+// total.  Lane l returns the total of value (l >> 1) (0 for (l >> 1) >= N).
+// About 4 instructions per value instead of 11 for N separate wave_sum calls.
+// All 64 lanes must be active.
+template <int N>
+__device__ __forceinline__ float wave_sum_multi(const float (&v)[N]) {
+    static_assert(N >= 1 && N <= 32, "wave_sum_multi handles up to 32 values");
+    const int lane = (int)(threadIdx.x & 63);
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    float a[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {            // partner lane ^ 32
+        const float lo = j < N ? v[j] : 0.f, hi = j + 16 < N ? v[j + 16] : 0.f;
+        a[j] = (b5 ? hi : lo) + __shfl_xor(b5 ? lo : hi, 32, 64);
+    }
+    float b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)               // partner lane ^ 16
+        b[j] = (b4 ? a[j + 8] : a[j]) + __shfl_xor(b4 ? a[j] : a[j + 8], 16, 64);
+    float c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)               // partner lane ^ 8: row_ror:8 within 16-lane rows
+        c[j] = (b3 ? b[j + 4] : b[j]) + dpp_mov<0x128>(b3 ? b[j] : b[j + 4]);
+    float d[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {             // partner lane ^ 4: from lane + 4 (row_ror:12) or lane - 4 (row_ror:4)
+        const float send = b2 ? c[j] : c[j + 2];
+        const float up = dpp_mov<0x12C>(send), down = dpp_mov<0x124>(send);
+        d[j] = (b2 ? c[j + 2] : c[j]) + (b2 ? down : up);
+    }
+    float e = (b1 ? d[1] : d[0]) + dpp_mov<0x4E>(b1 ? d[0] : d[1]);   // partner lane ^ 2
+    e += dpp_mov<0xB1>(e);                                              // partner lane ^ 1: plain sum
+    return e;
+}
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_movi(int v) {
     return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);

@@ -177,19 +177,19 @@ __device__ __forceinline__ void block_sum_store(const float (&val)[N], float *ds
     __shared__ float part[NW][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
-    float mine = 0.f;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const float s = wave_sum(val[i]);
-        if (lane == i) mine = s;
+    const float t = wave_sum_multi(val);      // lane 2i holds the wave's total of value i
+    const int i = lane >> 1;
+    if (NW == 1) {
+        if ((lane & 1) == 0 && i < N) dst[i] = t;
+        return;
     }
-    if (lane < N) part[w][lane] = mine;
+    if ((lane & 1) == 0 && i < N) part[w][i] = t;
     __syncthreads();
     if (threadIdx.x < N) {
-        float t = 0.f;
+        float s = 0.f;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) t += part[q][threadIdx.x];
-        dst[threadIdx.x] = t;
+        for (int q = 0; q < NW; ++q) s += part[q][threadIdx.x];
+        dst[threadIdx.x] = s;
     }
 }
 
@@ -205,8 +205,27 @@ __device__ __forceinline__ void block_sum_store(const float (&val)[N], float *ds
 // only flagged rows are stored.  Cost per pixel is N LDS adds however many
 // triangles share the tile, so dense meshes (about one triangle per pixel)
 // stay cheap.
+// The tile's bin range and this thread's entry of its first chunk, loaded
+// at the start of a tile kernel so that these dependent loads overlap the
+// per-pixel work instead of following it.  Loads are unconditional (clamped
+// indices) so that nothing waits for them before their use.
+struct BinHead {
+    unsigned b0, b1, si, pair;
+};
+__device__ __forceinline__ BinHead bin_head(int gt, int tid, const unsigned *__restrict__ tile_start,
+                                            const unsigned *__restrict__ bins,
+                                            const unsigned *__restrict__ bin_pair) {
+    BinHead h;
+    h.b0 = tile_start[gt];
+    h.b1 = tile_start[gt + 1];
+    const unsigned c = h.b1 > h.b0 ? min(h.b0 + (unsigned)tid, h.b1 - 1) : 0u;
+    h.si = bins[c];
+    h.pair = bin_pair[c];
+    return h;
+}
+
 template <int T, int N>
-__device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, const unsigned *__restrict__ tile_start,
+__device__ __forceinline__ void tile_pair_sums(const ViewConst &v, const BinHead &head,
                                                const unsigned *__restrict__ bins,
                                                const unsigned *__restrict__ bin_pair,
                                                const int (&key)[TileShape<T>::PPT],
@@ -217,20 +236,22 @@ __device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, const
     using TS = TileShape<T>;
     constexpr int CH = 64;
     __shared__ float part[CH * N];
-    __shared__ int ent[CH];
+    __shared__ __align__(16) int ent[CH];
     __shared__ unsigned slot[CH];
     __shared__ int hit[CH];
     const int tid = threadIdx.x;
-    const unsigned b0 = tile_start[gt], b1 = tile_start[gt + 1];
+    const unsigned b0 = head.b0, b1 = head.b1;
     bool mine = false;
 #pragma unroll
     for (int k = 0; k < TS::PPT; ++k) mine = mine || act[k];
     const bool any = __syncthreads_or(mine) != 0;
     for (unsigned c0 = b0; c0 < b1; c0 += CH) {
         const int n = (int)min((unsigned)CH, b1 - c0);
-        if (tid < n) {
-            ent[tid] = (int)(bins[c0 + tid] - (unsigned)v.setup_off);
-            slot[tid] = bin_pair[c0 + tid];
+        if (tid < CH) {
+            const bool first = c0 == b0;
+            // unused entries hold -2, which matches no key (background is -1)
+            ent[tid] = tid < n ? (int)((first ? head.si : bins[c0 + tid]) - (unsigned)v.setup_off) : -2;
+            slot[tid] = tid < n ? (first ? head.pair : bin_pair[c0 + tid]) : 0u;
             hit[tid] = 0;
         }
         if (any)
@@ -240,31 +261,75 @@ __device__ __forceinline__ void tile_pair_sums(const ViewConst &v, int gt, const
             int idx[TS::PPT];
 #pragma unroll
             for (int k = 0; k < TS::PPT; ++k) idx[k] = -1;
-            for (int e = 0; e < n; ++e) {
-                const int t = ent[e];
+            // fixed-length scan, four entries per LDS read, all reads in flight together
+            const int4 *ent4 = reinterpret_cast<const int4 *>(ent);
 #pragma unroll
-                for (int k = 0; k < TS::PPT; ++k)
-                    if (key[k] == t) idx[k] = e;
+            for (int e4 = 0; e4 < CH / 4; ++e4) {
+                const int4 t = ent4[e4];
+#pragma unroll
+                for (int k = 0; k < TS::PPT; ++k) {
+                    idx[k] = key[k] == t.x ? 4 * e4 : idx[k];
+                    idx[k] = key[k] == t.y ? 4 * e4 + 1 : idx[k];
+                    idx[k] = key[k] == t.z ? 4 * e4 + 2 : idx[k];
+                    idx[k] = key[k] == t.w ? 4 * e4 + 3 : idx[k];
+                }
             }
+            const int lane = tid & 63;
 #pragma unroll
             for (int k = 0; k < TS::PPT; ++k) {
-                if (idx[k] < 0) continue;
-                matched[k] = true;
-                if (!act[k]) continue;
-                hit[idx[k]] = 1;
-                float *row = part + idx[k] * N;
+                if (idx[k] >= 0) matched[k] = true;
+                bool todo = idx[k] >= 0 && act[k];
+                // A triangle owning many of the wave's pixels (a large ground
+                // polygon) is summed with one multi-value wave reduction; LDS
+                // atomics from that many lanes into one row would serialize.
+                for (int round = 0; round < 2; ++round) {
+                    const unsigned long long m = __ballot(todo);
+                    if (m == 0) break;
+                    const int leader = __ffsll(m) - 1;
+                    const int kk = __builtin_amdgcn_readlane(key[k], leader);
+                    const bool in = todo && key[k] == kk;
+                    if (__popcll(__ballot(in)) < 16) break;
+                    float masked[N];
 #pragma unroll
-                for (int i = 0; i < N; ++i)
-                    if (val[k][i] != 0.f) atomicAdd(row + i, val[k][i]);
+                    for (int i = 0; i < N; ++i) masked[i] = in ? val[k][i] : 0.f;
+                    const float t = wave_sum_multi(masked);
+                    const int e = __builtin_amdgcn_readlane(idx[k], leader);
+                    if ((lane & 1) == 0 && (lane >> 1) < N) atomicAdd(part + e * N + (lane >> 1), t);
+                    if (lane == leader) hit[e] = 1;
+                    todo = todo && !in;
+                }
+                if (todo) {
+                    hit[idx[k]] = 1;
+                    float *row = part + idx[k] * N;
+#pragma unroll
+                    for (int i = 0; i < N; ++i)
+                        if (val[k][i] != 0.f) atomicAdd(row + i, val[k][i]);
+                }
             }
             __syncthreads();
         }
         if (tid < n) pair_flag[slot[tid]] = (unsigned char)hit[tid];
-        if (any)
-            for (int f = tid; f < n * N; f += TS::NT) {
-                const int e = f / N, i = f - e * N;
-                if (hit[e]) pair_sums[(size_t)slot[e] * kNV + i] = part[f];
+        if (any) {
+            constexpr int G = 4;                          // LDS reads of G iterations in flight together
+            const int iters = (n * N + TS::NT - 1) / TS::NT;
+#pragma unroll 1
+            for (int it0 = 0; it0 < iters; it0 += G) {
+                float pv[G];
+                unsigned dst[G];
+                bool wr[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int f = tid + (it0 + g) * TS::NT;
+                    const int e = min(f / N, CH - 1), i = f - (f / N) * N;
+                    wr[g] = f < n * N && hit[e] != 0;
+                    dst[g] = slot[e] * (unsigned)kNV + (unsigned)i;
+                    pv[g] = part[min(f, CH * N - 1)];
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (wr[g]) pair_sums[dst[g]] = pv[g];
             }
+        }
         __syncthreads();
     }
 }
@@ -553,6 +618,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     const int lt = blk.x;
     if (lt >= cv.tiles_x * cv.tiles_y) return;     // whole workgroup
     const int gt = cv.tile_off + lt;
+    const BinHead head = bin_head(gt, (int)threadIdx.x, tile_start, bins, bin_pair);
     const int tx = lt % cv.tiles_x, ty = lt / cv.tiles_x;
     const int tid = threadIdx.x;
     int key[TS::PPT], pi[TS::PPT], pj[TS::PPT];
@@ -615,7 +681,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             block_sum_store<TS::NW>(accl[q], part_render + R.part_off + ((long long)q * ntiles + lt) * 22);
         }
     }
-    tile_pair_sums<T, kNV>(cv, gt, tile_start, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
+    tile_pair_sums<T, kNV>(cv, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(cv, key, val, act, matched, gtri);
 }
 
@@ -638,6 +704,7 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
     const int lt = blk.x;
     if (lt >= l.tiles_x * l.tiles_y) return;     // whole workgroup
     const int gt = l.tile_off + lt;
+    const BinHead head = bin_head(gt, (int)threadIdx.x, tile_start, bins, bin_pair);
     const int tx = lt % l.tiles_x, ty = lt / l.tiles_x;
     const unsigned long long *kv = keys + l.pix_off;
     const float *f0a = F0 + l.map_off, *f0b = F0 + l.map_off + plane;
@@ -737,7 +804,7 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
         }
     }
     block_sum_store<TS::NW>(accl, part_light + ((long long)l.part_off + lt) * 6);
-    tile_pair_sums<T, 18>(l, gt, tile_start, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
+    tile_pair_sums<T, 18>(l, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(l, key, val, act, matched, gtri);
 }
 
