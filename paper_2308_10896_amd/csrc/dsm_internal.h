@@ -83,7 +83,8 @@ struct DevCounters {
     unsigned long long overflow;
     unsigned long long bad_indices;
     unsigned int overflow_list_len;
-    unsigned int pad[7];
+    unsigned int big_bin_len;        // triangles binned a workgroup each
+    unsigned int pad[6];
 };
 
 // ----------------------------------------------------------------------------- helpers

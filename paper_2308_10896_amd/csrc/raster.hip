@@ -273,33 +273,19 @@ hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int
 
 // ----------------------------------------------------------------------------- binning
 
-__device__ __forceinline__ int find_tri(const unsigned *pair_off, int ntri, unsigned p) {
-    // largest i in [0, ntri) with pair_off[i] <= p
-    int lo = 0, hi = ntri - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pair_off[mid] <= p) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// FILL = false: count pairs per tile; FILL = true: scatter triangle indices.
-// Triangles whose pair range does not fit the bin capacity go to the
-// overflow path instead (decided per triangle, so never split).
+// Pairs of triangle i are the tiles of its bounding box in row-major order,
+// numbered pair_off[i] .. pair_off[i+1]-1.  FILL = false counts pairs per
+// tile; FILL = true scatters (triangle, pair) into the tile's bin.  Pairs
+// q0, q0 + step, ... of the triangle are handled by the calling thread.
 template <bool FILL>
-__global__ void bin_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
-                           const unsigned *__restrict__ pair_off, int ntri, unsigned capacity, int tile,
-                           unsigned *__restrict__ tile_count, const unsigned *__restrict__ tile_start,
-                           unsigned *__restrict__ bins, unsigned *__restrict__ bin_pair) {
-    const unsigned total = min(pair_off[ntri], capacity);
-    for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
-        const int i = find_tri(pair_off, ntri, p);
-        if (pair_off[i + 1] > capacity) continue;
-        const TriSetup &s = setup[i];
-        const ViewConst &v = views[s.pad2[0]];
-        const unsigned q = p - pair_off[i];
-        const int tx0 = s.bx0 / tile, tx1 = s.bx1 / tile, ty0 = s.by0 / tile;
-        const int ntx = tx1 - tx0 + 1;
+__device__ __forceinline__ void bin_pairs(const ViewConst *__restrict__ views, const TriSetup &s, int i, unsigned a,
+                                          unsigned b, int tile, unsigned q0, unsigned step,
+                                          unsigned *__restrict__ tile_count, const unsigned *__restrict__ tile_start,
+                                          unsigned *__restrict__ bins, unsigned *__restrict__ bin_pair) {
+    const ViewConst &v = views[s.pad2[0]];
+    const int tx0 = s.bx0 / tile, tx1 = s.bx1 / tile, ty0 = s.by0 / tile;
+    const int ntx = tx1 - tx0 + 1;
+    for (unsigned q = q0; q < b - a; q += step) {
         const int tx = tx0 + (int)(q % ntx), ty = ty0 + (int)(q / ntx);
         const int gt = v.tile_off + ty * v.tiles_x + tx;
         if (!FILL) {
@@ -307,8 +293,101 @@ __global__ void bin_kernel(const ViewConst *__restrict__ views, const TriSetup *
         } else {
             const unsigned slot = atomicAdd(&tile_count[gt], 1u);
             bins[tile_start[gt] + slot] = (unsigned)i;
-            bin_pair[tile_start[gt] + slot] = p;
+            bin_pair[tile_start[gt] + slot] = a + q;
         }
+    }
+}
+
+// Add each active lane's 1 to cnt[g], one atomic per distinct g in the wave
+// (neighbouring triangles of a mesh mostly share tiles), and return the
+// lane's slot: the old count plus its rank among the lanes with the same g.
+// All leaders' atomics are issued together, so the wave waits for one round
+// trip.  Uniform call (all 64 lanes).
+__device__ __forceinline__ unsigned wave_aggregated_slot(bool has, int g, unsigned *__restrict__ cnt) {
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long pending = __ballot(has);
+    int leader_of = lane;
+    unsigned rank = 0, size = 0;
+    while (pending) {
+        const int leader = __ffsll(pending) - 1;
+        const int gg = __builtin_amdgcn_readlane(g, leader);
+        const bool mine = has && g == gg;
+        const unsigned long long m = __ballot(mine);
+        pending &= ~m;
+        if (mine) {
+            leader_of = leader;
+            rank = (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            if (lane == leader) size = (unsigned)__popcll(m);
+        }
+    }
+    unsigned base = 0;
+    if (size) base = atomicAdd(&cnt[g], size);
+    base = (unsigned)__shfl((int)base, leader_of, 64);
+    return base + rank;
+}
+
+// Triangles with at most kBigBin pairs: one thread each.  Larger ones are
+// listed (count pass) and handled a workgroup each by bin_big_kernel.
+// Triangles whose pair range does not fit the bin capacity go to the
+// overflow path instead (decided per triangle, so never split).
+constexpr unsigned kBigBin = 32;
+
+template <bool FILL>
+__global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
+                                 const unsigned *__restrict__ pair_off, int ntri, unsigned capacity, int tile,
+                                 unsigned *__restrict__ tile_count, const unsigned *__restrict__ tile_start,
+                                 unsigned *__restrict__ bins, unsigned *__restrict__ bin_pair,
+                                 unsigned *__restrict__ big_list, DevCounters *counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned a = 0, b = 0;
+    if (i < ntri) {
+        a = pair_off[i];
+        b = pair_off[i + 1];
+        if (b > capacity) b = a;                           // overflow path
+        if (b - a > kBigBin) {
+            if (!FILL) big_list[atomicAdd(&counters->big_bin_len, 1u)] = (unsigned)i;
+            b = a;
+        }
+    }
+    const unsigned cnt = b - a;
+    if (__ballot(cnt > 0) == 0) return;                    // whole wave idle
+    TriSetup st{};
+    int tx0 = 0, ty0 = 0, ntx = 1, toff = 0, tiles_x = 0;
+    if (cnt > 0) {
+        st = setup[i];
+        const ViewConst &v = views[st.pad2[0]];
+        tx0 = st.bx0 / tile;
+        ty0 = st.by0 / tile;
+        ntx = st.bx1 / tile - tx0 + 1;
+        toff = v.tile_off;
+        tiles_x = v.tiles_x;
+    }
+    for (unsigned q = 0; __ballot(q < cnt) != 0; ++q) {   // uniform loop: the wave's largest count
+        const bool has = q < cnt;
+        const int gt = has ? toff + (ty0 + (int)(q / ntx)) * tiles_x + tx0 + (int)(q % ntx) : 0;
+        if (!FILL) {
+            (void)wave_aggregated_slot(has, gt, tile_count);
+        } else {
+            const unsigned slot = wave_aggregated_slot(has, gt, tile_count);
+            if (has) {
+                bins[tile_start[gt] + slot] = (unsigned)i;
+                bin_pair[tile_start[gt] + slot] = a + q;
+            }
+        }
+    }
+}
+
+template <bool FILL>
+__global__ void bin_big_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
+                               const unsigned *__restrict__ pair_off, int tile, unsigned *__restrict__ tile_count,
+                               const unsigned *__restrict__ tile_start, unsigned *__restrict__ bins,
+                               unsigned *__restrict__ bin_pair, const unsigned *__restrict__ big_list,
+                               const DevCounters *counters) {
+    const unsigned n = counters->big_bin_len;
+    for (unsigned o = blockIdx.x; o < n; o += gridDim.x) {
+        const int i = (int)big_list[o];
+        bin_pairs<FILL>(views, setup[i], i, pair_off[i], pair_off[i + 1], tile, threadIdx.x, blockDim.x, tile_count,
+                        tile_start, bins, bin_pair);
     }
 }
 
@@ -495,14 +574,27 @@ hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const u
                           unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
                           unsigned *tile_cursor, unsigned *scan_scratch, int ntiles, unsigned *bins,
                           unsigned *bin_pair, unsigned *overflow_list, DevCounters *counters, hipStream_t s) {
-    const int grid = 2048;
     hipLaunchKernelGGL(pairs_total_kernel, dim3(1), dim3(1), 0, s, pair_off, ntri, counters);
-    hipLaunchKernelGGL(bin_kernel<false>, dim3(grid), dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
-                       tile_count, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr);
+    // the list of large triangles lives in overflow_list until the overflow list is built below
+    const dim3 tgrid((ntri + 255) / 256);
+    const dim3 bgrid(1024);
+    if (ntri > 0) {
+        hipLaunchKernelGGL(bin_small_kernel<false>, tgrid, dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
+                           tile_count, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
+                           overflow_list, counters);
+        hipLaunchKernelGGL(bin_big_kernel<false>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile, tile_count,
+                           (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
+                           (const unsigned *)overflow_list, (const DevCounters *)counters);
+    }
     hipError_t e = launch_scan(tile_count, tile_start, scan_scratch, ntiles, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bin_kernel<true>, dim3(grid), dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
-                       tile_cursor, (const unsigned *)tile_start, bins, bin_pair);
+    if (ntri > 0) {
+        hipLaunchKernelGGL(bin_small_kernel<true>, tgrid, dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
+                           tile_cursor, (const unsigned *)tile_start, bins, bin_pair, overflow_list, counters);
+        hipLaunchKernelGGL(bin_big_kernel<true>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile, tile_cursor,
+                           (const unsigned *)tile_start, bins, bin_pair, (const unsigned *)overflow_list,
+                           (const DevCounters *)counters);
+    }
     if (ntri > 0)
         hipLaunchKernelGGL(overflow_list_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
                            overflow_list, counters);
