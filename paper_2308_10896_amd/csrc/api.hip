@@ -298,6 +298,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sv_clip = o; o = align_up(o + 16 * (size_t)clip);
     p->sv_setup = o; o = align_up(o + sizeof(TriSetup) * (size_t)tri);
     p->sv_sil = o; o = align_up(o + (size_t)tri);
+    p->sv_tv = o; o = align_up(o + sizeof(TriVerts) * (size_t)std::max<long long>(Ft, 1));
     p->sv_F0 = o; o = align_up(o + 4 * (size_t)maps);
     p->sv_M = o; o = align_up(o + 4 * (size_t)maps);
     p->sv_img0 = o; o = align_up(o + 4 * (size_t)img);
@@ -466,6 +467,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     float4 *clip = at<float4>(saved, p->sv_clip);
     TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
     unsigned char *silm = at<unsigned char>(saved, p->sv_sil);
+    TriVerts *tv = at<TriVerts>(saved, p->sv_tv);
     float *F0 = at<float>(saved, p->sv_F0);
     float *Mm = at<float>(saved, p->sv_M);
     float *img0 = at<float>(saved, p->sv_img0);
@@ -474,6 +476,8 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
+    DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts, tv,
+                             s));
     DSM_TRY(launch_setup(p->views_d, p->nviews, p->max_faces, p->faces_d, clip, setup, pair_cnt, p->tile, cnt, s));
     DSM_TRY(launch_silhouettes(p->views_d, p->nviews, p->max_faces, p->adj_d, setup, silm, s));
     DSM_MARK(DSM_STAGE_BIN);
@@ -484,7 +488,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_raster(p->views_d, p->tile_view_d, p->ntiles, p->tile, setup, tile_start, bins, overflow, cnt, cnt,
                           keys, s));
     DSM_MARK(DSM_STAGE_RESOLVE);
-    DSM_TRY(launch_resolve(p->views_d, p->L, p->max_light_texels, p->faces_d, verts, clip, keys, F0, s));
+    DSM_TRY(launch_resolve(p->views_d, p->L, p->max_light_texels, tv, keys, F0, s));
     DSM_MARK(DSM_STAGE_LIGHT_AA);
     DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, silm,
                               verts, keys, F0, F1, 2, s));
@@ -492,8 +496,8 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, F1, Mm, false, g.R, s));
     DSM_MARK(DSM_STAGE_LOOKUP);
-    DSM_TRY(launch_lookup(p->views_d, p->renders_d, p->R, p->max_cam_pix, p->render_lights_d, p->faces_d, verts,
-                          albedo, clip, keys, Mm, img0, p->C, s));
+    DSM_TRY(launch_lookup(p->views_d, p->renders_d, p->R, p->max_cam_pix, p->render_lights_d, tv, albedo, keys, Mm,
+                          img0, p->C, s));
     DSM_MARK(DSM_STAGE_CAMERA_AA);
     DSM_TRY(launch_aa_forward(false, p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
                               verts, keys, img0, images, p->C, s));
@@ -507,6 +511,7 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     const float4 *clip = at<float4>(saved, p->sv_clip);
     const TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
     const unsigned char *silm = at<unsigned char>(saved, p->sv_sil);
+    const TriVerts *tv = at<TriVerts>(saved, p->sv_tv);
     const float *F0 = at<float>(saved, p->sv_F0);
     const float *Mm = at<float>(saved, p->sv_M);
     const float *img0 = at<float>(saved, p->sv_img0);
@@ -540,14 +545,14 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_MARK(DSM_STAGE_LOOKUP_ADJ);
     DSM_TRY(launch_lookup_backward(p->tile, p->views_d, p->L, p->Cm, p->max_cam_tiles, p->max_lights_per_render,
                                    p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
-                                   p->faces_d, verts, albedo, clip, keys, Mm, gimg0, gM, setup, tile_start, bins,
+                                   p->faces_d, verts, albedo, tv, keys, Mm, gimg0, gM, setup, tile_start, bins,
                                    bin_pair, pair_flag, pair_sums, gtri, part_render, p->C, s));
     DSM_MARK(DSM_STAGE_FILTER_ADJ);
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
     DSM_MARK(DSM_STAGE_LIGHT_ADJ);
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
-                                  clip, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,
+                                  tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,
                                   part_light,
                                   s));
     DSM_MARK(DSM_STAGE_VERTEX_GRAD);

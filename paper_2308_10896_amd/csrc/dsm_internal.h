@@ -181,6 +181,23 @@ __device__ __forceinline__ Blk xcd_block2() {
     return Blk{lin % gx, lin / gx};
 }
 
+// Clip coordinates M [x, 1] in the fixed operation order every kernel uses
+// (no contraction), so that recomputing them anywhere is bit-identical.
+__device__ __forceinline__ float4 clip_of(const float *M, float x, float y, float z) {
+    float4 c;
+    c.x = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+    c.y = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
+    c.z = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
+    c.w = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
+    return c;
+}
+
+// World positions of a triangle's three corners, packed as three float4
+// (x0 y0 z0 x1 | y1 z1 x2 y2 | z2 - - -), one record per face of the batch.
+struct TriVerts {
+    float4 a, b, c;
+};
+
 __device__ __forceinline__ void atomic_add_f32(float *p, float v) {
     if (v != 0.0f) atomicAdd(p, v);
 }
@@ -218,15 +235,16 @@ hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntile
                          const unsigned *tile_start, const unsigned *bins, const unsigned *overflow_list,
                          const DevCounters *counters_ro, DevCounters *counters, unsigned long long *keys,
                          hipStream_t s);
-hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const int *faces, const float *verts,
-                          const float4 *clip, const unsigned long long *keys, float *F0, hipStream_t s);
+hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const TriVerts *tv,
+                          const unsigned long long *keys, float *F0, hipStream_t s);
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
                              const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
                              const unsigned long long *keys, const float *src, float *dst, int C, hipStream_t s);
 hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
-                         const int *render_lights, const int *faces, const float *verts, const float *albedo,
-                         const float4 *clip, const unsigned long long *keys, const float *maps, float *img0, int C,
-                         hipStream_t s);
+                         const int *render_lights, const TriVerts *tv, const float *albedo,
+                         const unsigned long long *keys, const float *maps, float *img0, int C, hipStream_t s);
+hipError_t launch_tri_verts(const int *scene_vert_off, const int *scene_face_off, int B, int max_faces,
+                            const int *faces, const float *verts, TriVerts *tv, hipStream_t s);
 // backward
 hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
                                      const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
@@ -235,12 +253,12 @@ hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *
 hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int Cm, int max_tiles, int max_lights,
                                   const RenderConst *renders, const int *cam_renders_off, const int *cam_renders,
                                   const int *render_lights, const int *faces, const float *verts, const float *albedo,
-                                  const float4 *clip, const unsigned long long *keys, const float *maps,
+                                  const TriVerts *tv, const unsigned long long *keys, const float *maps,
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
                                   const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
                                   float *pair_sums, float *gtri, float *part_render, int C, hipStream_t s);
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
-                                 const int *faces, const unsigned char *silm, const float *verts, const float4 *clip,
+                                 const int *faces, const unsigned char *silm, const float *verts, const TriVerts *tv,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,

@@ -362,22 +362,17 @@ struct MapHit {
 template <int MAXL, bool DIRECT>
 __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const RenderConst &R,
                                                   const ViewConst *__restrict__ views,
-                                                  const int *__restrict__ render_lights, const int *__restrict__ faces,
-                                                  const float *__restrict__ verts, const float *__restrict__ albedo,
-                                                  const float4 *__restrict__ clip, const float *__restrict__ maps,
+                                                  const int *__restrict__ render_lights,
+                                                  const TriVerts *__restrict__ tv, const float *__restrict__ albedo,
+                                                  const float *__restrict__ maps,
                                                   float *__restrict__ gmaps, int i, int j, int tri, const float g[3],
                                                   int C, float (&vals)[21], float (&accl)[MAXL][22],
                                                   MapHit (&hits)[MAXL]) {
-    const int *f = faces + 3 * (size_t)(cv.face_off + tri);
+    const TriVerts r = tv[cv.face_off + tri];
+    const float v0[3] = {r.a.x, r.a.y, r.a.z}, v1[3] = {r.a.w, r.b.x, r.b.y}, v2[3] = {r.b.z, r.b.w, r.c.x};
     const float px = ndc_c(i, cv.W), py = -ndc_c(j, cv.H);
-    const float4 c0 = clip[cv.clip_off + f[0]], c1 = clip[cv.clip_off + f[1]], c2 = clip[cv.clip_off + f[2]];
-    float v0[3], v1[3], v2[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        v0[k] = verts[3 * (size_t)(cv.vert_off + f[0]) + k];
-        v1[k] = verts[3 * (size_t)(cv.vert_off + f[1]) + k];
-        v2[k] = verts[3 * (size_t)(cv.vert_off + f[2]) + k];
-    }
+    const float4 c0 = clip_of(cv.M, v0[0], v0[1], v0[2]), c1 = clip_of(cv.M, v1[0], v1[1], v1[2]),
+                 c2 = clip_of(cv.M, v2[0], v2[1], v2[2]);
     const BaryFull b = bary_full(c0, c1, c2, px, py);
     const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
     const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
@@ -606,7 +601,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     const ViewConst *__restrict__ views, int L, const RenderConst *__restrict__ renders,
     const int *__restrict__ cam_renders_off, const int *__restrict__ cam_renders,
     const int *__restrict__ render_lights, const int *__restrict__ faces, const float *__restrict__ verts,
-    const float *__restrict__ albedo, const float4 *__restrict__ clip, const unsigned long long *__restrict__ keys,
+    const float *__restrict__ albedo, const TriVerts *__restrict__ tv, const unsigned long long *__restrict__ keys,
     const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
     const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
@@ -657,7 +652,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             for (int c = 0; c < C; ++c) g[c] = gimg0[R.img_off + p * C + c];
             if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) continue;
             float tmp[kNV];
-            lookup_pixel_grad<MAXL, kDirect>(cv, R, views, render_lights, faces, verts, albedo, clip, maps, gmaps,
+            lookup_pixel_grad<MAXL, kDirect>(cv, R, views, render_lights, tv, albedo, maps, gmaps,
                                              pi[k], pj[k], key[k], g, C, tmp, accl, hits[k]);
             act[k] = true;
 #pragma unroll
@@ -690,7 +685,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
 template <int T>
 __global__ __launch_bounds__(256) void light_backward_kernel(
     const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup, const int *__restrict__ faces,
-    const unsigned char *__restrict__ silm, const float *__restrict__ verts, const float4 *__restrict__ clip,
+    const unsigned char *__restrict__ silm, const float *__restrict__ verts, const TriVerts *__restrict__ tv,
     const unsigned long long *__restrict__ keys, const float *__restrict__ F0, const float *__restrict__ gF1,
     float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
@@ -760,15 +755,10 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
         // resolve^T: F0 = (z, z^2), z = d(x) / far
         act[k] = key[k] >= 0 && (g0 != 0.f || g1 != 0.f);
         if (act[k]) {
-            const int *f = faces + 3 * (size_t)(l.face_off + key[k]);
-            const float4 c0 = clip[l.clip_off + f[0]], c1 = clip[l.clip_off + f[1]], c2 = clip[l.clip_off + f[2]];
-            float v0[3], v1[3], v2[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                v0[q] = verts[3 * (size_t)(l.vert_off + f[0]) + q];
-                v1[q] = verts[3 * (size_t)(l.vert_off + f[1]) + q];
-                v2[q] = verts[3 * (size_t)(l.vert_off + f[2]) + q];
-            }
+            const TriVerts r = tv[l.face_off + key[k]];
+            const float v0[3] = {r.a.x, r.a.y, r.a.z}, v1[3] = {r.a.w, r.b.x, r.b.y}, v2[3] = {r.b.z, r.b.w, r.c.x};
+            const float4 c0 = clip_of(l.M, v0[0], v0[1], v0[2]), c1 = clip_of(l.M, v1[0], v1[1], v1[2]),
+                         c2 = clip_of(l.M, v2[0], v2[1], v2[2]);
             const float px = ndc_c(i, S), py = -ndc_c(j, S);
             const BaryFull b = bary_full(c0, c1, c2, px, py);
             const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
@@ -1097,7 +1087,7 @@ hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *
 hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int Cm, int max_tiles, int max_lights,
                                   const RenderConst *renders, const int *cam_renders_off, const int *cam_renders,
                                   const int *render_lights, const int *faces, const float *verts, const float *albedo,
-                                  const float4 *clip, const unsigned long long *keys, const float *maps,
+                                  const TriVerts *tv, const unsigned long long *keys, const float *maps,
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
                                   const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
                                   float *pair_sums, float *gtri, float *part_render, int C, hipStream_t s) {
@@ -1105,7 +1095,7 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
     const dim3 grid(max_tiles, Cm);
 #define DSM_LB(TT, ML)                                                                                              \
     hipLaunchKernelGGL((lookup_backward_kernel<TT, ML>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,   \
-                       cam_renders_off, cam_renders, render_lights, faces, verts, albedo, clip, keys, maps, gimg0,   \
+                       cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0,     \
                        gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C)
 #define DSM_LB_T(TT)                                                  \
     if (max_lights <= 1) DSM_LB(TT, 1);                               \
@@ -1120,7 +1110,7 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
 }
 
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
-                                 const int *faces, const unsigned char *silm, const float *verts, const float4 *clip,
+                                 const int *faces, const unsigned char *silm, const float *verts, const TriVerts *tv,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
@@ -1129,7 +1119,7 @@ hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int ma
     const dim3 grid(max_tiles, L);
 #define DSM_LIB(TT)                                                                                                  \
     hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, silm,  \
-                       verts, clip, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,   \
+                       verts, tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,     \
                        part_light)
     if (tile == 8) DSM_LIB(8);
     else if (tile == 16) DSM_LIB(16);

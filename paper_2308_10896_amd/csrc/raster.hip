@@ -74,13 +74,33 @@ __global__ void transform_kernel(const ViewConst *__restrict__ views, const floa
     if (i >= v.nverts) return;
     const float *p = verts + 3 * (size_t)(v.vert_off + i);
     const float x = p[0], y = p[1], z = p[2];
-    const float *M = v.M;
-    float4 c;
-    c.x = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
-    c.y = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
-    c.z = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
-    c.w = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
-    clip[v.clip_off + i] = c;
+    clip[v.clip_off + i] = clip_of(v.M, x, y, z);
+}
+
+// One TriVerts record per face: the corners' world positions gathered once,
+// so that per-pixel passes fetch one record instead of face -> vertices.
+__global__ void tri_verts_kernel(const int *__restrict__ scene_vert_off, const int *__restrict__ scene_face_off,
+                                 const int *__restrict__ faces, const float *__restrict__ verts,
+                                 TriVerts *__restrict__ tv) {
+    const int b = blockIdx.y;
+    const int f = scene_face_off[b] + blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= scene_face_off[b + 1]) return;
+    const float *v0 = verts + 3 * (size_t)(scene_vert_off[b] + faces[3 * (size_t)f]);
+    const float *v1 = verts + 3 * (size_t)(scene_vert_off[b] + faces[3 * (size_t)f + 1]);
+    const float *v2 = verts + 3 * (size_t)(scene_vert_off[b] + faces[3 * (size_t)f + 2]);
+    TriVerts r;
+    r.a = make_float4(v0[0], v0[1], v0[2], v1[0]);
+    r.b = make_float4(v1[1], v1[2], v2[0], v2[1]);
+    r.c = make_float4(v2[2], 0.f, 0.f, 0.f);
+    tv[f] = r;
+}
+
+hipError_t launch_tri_verts(const int *scene_vert_off, const int *scene_face_off, int B, int max_faces,
+                            const int *faces, const float *verts, TriVerts *tv, hipStream_t s) {
+    if (B == 0 || max_faces == 0) return hipSuccess;
+    hipLaunchKernelGGL(tri_verts_kernel, dim3((max_faces + 255) / 256, B), dim3(256), 0, s, scene_vert_off,
+                       scene_face_off, faces, verts, tv);
+    return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------- setup

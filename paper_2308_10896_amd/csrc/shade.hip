@@ -53,8 +53,7 @@ __device__ __forceinline__ float light_depth(const ViewConst &l, float x, float 
 
 // ----------------------------------------------------------------------------- resolve
 
-__global__ void resolve_kernel(const ViewConst *__restrict__ views, const int *__restrict__ faces,
-                               const float *__restrict__ verts, const float4 *__restrict__ clip,
+__global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVerts *__restrict__ tv,
                                const unsigned long long *__restrict__ keys, float *__restrict__ F0) {
     const ViewConst &l = views[blockIdx.y];
     const int S = l.W;
@@ -64,14 +63,13 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const int *_
     float z = 1.0f, z2 = 1.0f;
     if (key != kBgKey) {
         const int tri = (int)(unsigned)key;
-        const int *f = faces + 3 * (size_t)(l.face_off + tri);
+        const TriVerts r = tv[l.face_off + tri];
+        const float v0[3] = {r.a.x, r.a.y, r.a.z}, v1[3] = {r.a.w, r.b.x, r.b.y}, v2[3] = {r.b.z, r.b.w, r.c.x};
         const int i = t % S, j = t / S;
         const float px = ndc_centre(i, S), py = -ndc_centre(j, S);
-        const float4 c0 = clip[l.clip_off + f[0]], c1 = clip[l.clip_off + f[1]], c2 = clip[l.clip_off + f[2]];
+        const float4 c0 = clip_of(l.M, v0[0], v0[1], v0[2]), c1 = clip_of(l.M, v1[0], v1[1], v1[2]),
+                     c2 = clip_of(l.M, v2[0], v2[1], v2[2]);
         const Bary b = persp_bary(c0, c1, c2, px, py);
-        const float *v0 = verts + 3 * (size_t)(l.vert_off + f[0]);
-        const float *v1 = verts + 3 * (size_t)(l.vert_off + f[1]);
-        const float *v2 = verts + 3 * (size_t)(l.vert_off + f[2]);
         const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
         const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
         const float zz = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
@@ -157,9 +155,8 @@ __device__ __forceinline__ Fetch bilinear2(const float *__restrict__ maps, long 
 }
 
 __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
-                              const int *__restrict__ render_lights, const int *__restrict__ faces,
-                              const float *__restrict__ verts, const float *__restrict__ albedo,
-                              const float4 *__restrict__ clip, const unsigned long long *__restrict__ keys,
+                              const int *__restrict__ render_lights, const TriVerts *__restrict__ tv,
+                              const float *__restrict__ albedo, const unsigned long long *__restrict__ keys,
                               const float *__restrict__ maps, float *__restrict__ img0, int C) {
     const RenderConst &R = renders[blockIdx.y];
     const ViewConst &cv = views[R.camera_view];
@@ -173,14 +170,13 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
         return;
     }
     const int tri = (int)(unsigned)key;
-    const int *f = faces + 3 * (size_t)(cv.face_off + tri);
+    const TriVerts r = tv[cv.face_off + tri];
+    const float v0[3] = {r.a.x, r.a.y, r.a.z}, v1[3] = {r.a.w, r.b.x, r.b.y}, v2[3] = {r.b.z, r.b.w, r.c.x};
     const int i = p % W, j = p / W;
     const float px = ndc_centre(i, W), py = -ndc_centre(j, H);
-    const float4 c0 = clip[cv.clip_off + f[0]], c1 = clip[cv.clip_off + f[1]], c2 = clip[cv.clip_off + f[2]];
+    const float4 c0 = clip_of(cv.M, v0[0], v0[1], v0[2]), c1 = clip_of(cv.M, v1[0], v1[1], v1[2]),
+                 c2 = clip_of(cv.M, v2[0], v2[1], v2[2]);
     const Bary b = persp_bary(c0, c1, c2, px, py);
-    const float *v0 = verts + 3 * (size_t)(cv.vert_off + f[0]);
-    const float *v1 = verts + 3 * (size_t)(cv.vert_off + f[1]);
-    const float *v2 = verts + 3 * (size_t)(cv.vert_off + f[2]);
     const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
     const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
     const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
@@ -239,11 +235,10 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
 
 // ----------------------------------------------------------------------------- launchers
 
-hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const int *faces, const float *verts,
-                          const float4 *clip, const unsigned long long *keys, float *F0, hipStream_t s) {
+hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const TriVerts *tv,
+                          const unsigned long long *keys, float *F0, hipStream_t s) {
     if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(resolve_kernel, dim3((max_texels + 255) / 256, L), dim3(256), 0, s, views, faces, verts, clip,
-                       keys, F0);
+    hipLaunchKernelGGL(resolve_kernel, dim3((max_texels + 255) / 256, L), dim3(256), 0, s, views, tv, keys, F0);
     return hipGetLastError();
 }
 
@@ -262,12 +257,11 @@ hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderCon
 }
 
 hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
-                         const int *render_lights, const int *faces, const float *verts, const float *albedo,
-                         const float4 *clip, const unsigned long long *keys, const float *maps, float *img0, int C,
-                         hipStream_t s) {
+                         const int *render_lights, const TriVerts *tv, const float *albedo,
+                         const unsigned long long *keys, const float *maps, float *img0, int C, hipStream_t s) {
     if (R == 0) return hipSuccess;
     hipLaunchKernelGGL(lookup_kernel, dim3((max_pix + 255) / 256, R), dim3(256), 0, s, views, renders, render_lights,
-                       faces, verts, albedo, clip, keys, maps, img0, C);
+                       tv, albedo, keys, maps, img0, C);
     return hipGetLastError();
 }
 
