@@ -33,20 +33,20 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this
 # script (profiles/cfg2_hbm_traffic_pmc.md).  Each counter is scaled by what
 # it reads for a plain 128 MiB device-to-device copy in the same runs
-# (FETCH_SIZE reads 65550.4 KiB and WRITE_SIZE 131072 KiB for 131072 KiB
+# (FETCH_SIZE reads 65548.0 KiB and WRITE_SIZE 131072 KiB for 131072 KiB
 # moved each way).  A record is only used while the kernel's sources hash to
 # the value they had when the counters were taken.
-PMC_FETCH_SCALE = 131072.0 / 65550.4
+PMC_FETCH_SCALE = 131072.0 / 65548.0
 PMC_WRITE_SCALE = 131072.0 / 131072.0
 PMC_TRAFFIC = {
-    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65824.9, write_kib=131072.0,
-                   sources=('blur.hip', 'dsm_internal.h'), sha1='81724dd5bf71c42b'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65697.8, write_kib=131072.0,
-                       sources=('blur.hip', 'dsm_internal.h'), sha1='81724dd5bf71c42b'),
-    'lookup': dict(kernel='lookup_kernel', fetch_kib=153613.3, write_kib=65536.0,
-                   sources=('shade.hip', 'dsm_internal.h'), sha1='2302679008d0f815'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel<8, 1>', fetch_kib=351212.8, write_kib=129501.4,
-                       sources=('grad.hip', 'dsm_internal.h'), sha1='1aaa6eff6cc949ee'),
+    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65882.8, write_kib=131072.0,
+                   sources=('blur.hip', 'dsm_internal.h'), sha1='56979c1b3c0f97dd'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65692.2, write_kib=131072.0,
+                       sources=('blur.hip', 'dsm_internal.h'), sha1='56979c1b3c0f97dd'),
+    'lookup': dict(kernel='lookup_kernel', fetch_kib=158527.9, write_kib=65536.0,
+                   sources=('shade.hip', 'dsm_internal.h'), sha1='b02fb41723e66ce8'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel<8, 1>', fetch_kib=119337.2, write_kib=108520.3,
+                       sources=('grad.hip', 'dsm_internal.h'), sha1='bcb1ef7c5f4b51e4'),
 }
 
 
