@@ -513,7 +513,23 @@ __global__ __launch_bounds__(kRasterThreads) void raster_kernel(
             tris[tid] = load_raster_tri(setup[si], si - (unsigned)v.setup_off);
         }
         __syncthreads();
-        for (unsigned q = 0; q < n; ++q) {
+        // four entries per step: their independent edge-function / depth
+        // chains interleave, which hides latency at a given occupancy
+        unsigned q = 0;
+        for (; q + 4 <= n; q += 4) {
+            const RasterTri &r0 = tris[q], &r1 = tris[q + 1], &r2 = tris[q + 2], &r3 = tris[q + 3];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const unsigned long long k0 = sample_key(r0, pi[k], pj[k]);
+                const unsigned long long k1 = sample_key(r1, pi[k], pj[k]);
+                const unsigned long long k2 = sample_key(r2, pi[k], pj[k]);
+                const unsigned long long k3 = sample_key(r3, pi[k], pj[k]);
+                const unsigned long long a01 = k0 < k1 ? k0 : k1, a23 = k2 < k3 ? k2 : k3;
+                const unsigned long long a = a01 < a23 ? a01 : a23;
+                best[k] = a < best[k] ? a : best[k];
+            }
+        }
+        for (; q < n; ++q) {
             const RasterTri &r = tris[q];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
