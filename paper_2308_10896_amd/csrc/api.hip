@@ -244,7 +244,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         rc.img_off = img;
         rc.pix_off = p->views_h[L + x.camera].pix_off;
         rc.part_off = (int)part_render;
-        part_render += 22LL * x.light_count * p->views_h[L + x.camera].tiles_x * p->views_h[L + x.camera].tiles_y;
+        part_render += 3LL * x.light_count * p->views_h[L + x.camera].tiles_x * p->views_h[L + x.camera].tiles_y;
         img += (long long)rc.W * rc.H * p->C;
         p->renders_h[r] = rc;
     }
@@ -328,8 +328,9 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_pair_sums = o; o = align_up(o + 4 * 21 * (size_t)p->capacity);
     p->sc_gtri = o; o = align_up(o + 4 * 21 * ((size_t)tri + 1));
     p->sc_biglist = o; o = align_up(o + 4 * ((size_t)tri + 1));
-    p->sc_part_light = o; o = align_up(o + 4 * 6 * (size_t)(part_light + 1));
-    p->sc_part_gm = o; o = align_up(o + 4 * 16 * (size_t)(part_gm + 1));
+    p->sc_part_light = o; o = align_up(o + 4 * 3 * (size_t)(part_light + 1));
+    p->sc_part_gm = o; o = align_up(o + 4 * 3 * (size_t)(part_gm + 1));
+    p->sc_jac = o; o = align_up(o + 4 * (size_t)kJac * (size_t)std::max(L, 1));
     p->sc_part_render = o; o = align_up(o + 4 * (size_t)(part_render + 1));
     p->scratch_bytes = o;
 
@@ -474,7 +475,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
 
     DSM_MARK(DSM_STAGE_SETUP);
     DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));
-    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts, tv,
                              s));
@@ -526,7 +527,6 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     unsigned *big_count = at<unsigned>(scratch, p->sc_bigcount);
     float *gM = at<float>(scratch, p->sc_gM);
     float4 *gclip = at<float4>(scratch, p->sc_gclip);
-    float *glight = at<float>(scratch, p->sc_glight);
     float *gF1 = at<float>(scratch, p->sc_gF1);
     float *pair_sums = at<float>(scratch, p->sc_pair_sums);
     float *gtri = at<float>(scratch, p->sc_gtri);
@@ -534,11 +534,12 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     float *part_light = at<float>(scratch, p->sc_part_light);
     float *part_gm = at<float>(scratch, p->sc_part_gm);
     float *part_render = at<float>(scratch, p->sc_part_render);
+    float *jac = at<float>(scratch, p->sc_jac);
 
     DSM_MARK(DSM_STAGE_BWD_SETUP);
     DSM_TRY(zero_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, s));   // big count, gM, silhouette gclip
     DSM_TRY(launch_overflow_rows_zero(overflow, cnt, gtri, s));
-    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, s));
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, jac, s));
     DSM_MARK(DSM_STAGE_CAMERA_AA_ADJ);
     DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
                                       verts, keys, img0, gimg, gimg0, gclip, p->C, s));
@@ -546,25 +547,23 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_TRY(launch_lookup_backward(p->tile, p->views_d, p->L, p->Cm, p->max_cam_tiles, p->max_lights_per_render,
                                    p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
                                    p->faces_d, verts, albedo, tv, keys, Mm, gimg0, gM, setup, tile_start, bins,
-                                   bin_pair, pair_flag, pair_sums, gtri, part_render, p->C, s));
+                                   bin_pair, pair_flag, pair_sums, gtri, part_render, p->C, jac, s));
     DSM_MARK(DSM_STAGE_FILTER_ADJ);
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
     DSM_MARK(DSM_STAGE_LIGHT_ADJ);
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
                                   tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,
-                                  part_light,
-                                  s));
+                                  part_light, jac, s));
     DSM_MARK(DSM_STAGE_VERTEX_GRAD);
     DSM_TRY(launch_vertex_gradients(p->views_d, p->L, p->B, p->max_scene_verts, p->max_scene_faces, p->ntri,
                                     p->capacity, p->scene_vert_off_d, p->scene_face_off_d, p->scene_views_off_d,
                                     p->scene_views_d, p->vc_off_d, p->vc_list_d, pair_off, pair_flag, pair_sums, gtri,
                                     big_list,
-                                    big_count, verts, gclip, gverts, part_gm, galbedo, p->C, s));
+                                    big_count, verts, gclip, gverts, part_gm, galbedo, p->C, jac, s));
     DSM_MARK(DSM_STAGE_LIGHT_GRAD);
     DSM_TRY(launch_glight_reduce(p->views_d, p->L, p->renders_d, p->light_renders_off_d, p->light_renders_d, part_gm,
-                                 part_light, part_render, glight, s));
-    DSM_TRY(launch_light_param_grad(p->light_cams_d, lparams, glight, glparams, p->L, s));
+                                 part_light, part_render, glparams, s));
     DSM_MARK(DSM_STAGE_COUNT);
     return DSM_OK;
 }

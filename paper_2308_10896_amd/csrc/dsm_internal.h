@@ -216,9 +216,10 @@ int blur_tiles_x(int S);
 bool valid_filter(int S, int filter, int k);
 
 struct CamStatic;
-hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, hipStream_t s);
-hipError_t launch_light_param_grad(const CamStatic *cams, const float *params, const float *glight, float *gparams,
-                                   int L, hipStream_t s);
+// Jacobian of a light frame (M[16], pos[3], dir[3]) w.r.t. its three parameter components, [22][3].
+constexpr int kJac = 66;
+hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
+                               hipStream_t s);
 hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
                             hipStream_t s);
 hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj, TriSetup *setup,
@@ -256,24 +257,25 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const TriVerts *tv, const unsigned long long *keys, const float *maps,
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
                                   const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
-                                  float *pair_sums, float *gtri, float *part_render, int C, hipStream_t s);
+                                  float *pair_sums, float *gtri, float *part_render, int C, const float *jac,
+                                  hipStream_t s);
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const unsigned char *silm, const float *verts, const TriVerts *tv,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
-                                 hipStream_t s);
+                                 const float *jac, hipStream_t s);
 hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max_verts, int max_faces, int ntri,
                                    unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
                                    const int *scene_views_off, const int *scene_views, const int *vc_off,
                                    const int *vc_list, const unsigned *pair_off, const unsigned char *pair_flag,
                                    const float *pair_sums, float *gtri,
                                    unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
-                                   float *gverts, float *part_gm, float *galbedo, int C, hipStream_t s);
+                                   float *gverts, float *part_gm, float *galbedo, int C, const float *jac, hipStream_t s);
 hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *counters, float *gtri, hipStream_t s);
 hipError_t launch_glight_reduce(const ViewConst *views, int L, const RenderConst *renders,
                                 const int *light_renders_off, const int *light_renders, const float *part_gm,
-                                const float *part_light, const float *part_render, float *glight, hipStream_t s);
+                                const float *part_light, const float *part_render, float *gparams, hipStream_t s);
 hipError_t launch_pose(const int *scene_vert_off, const int *pose_counts, const float *pose_centers, int B,
                        int max_verts, const float *local, const float *poses, float *world, hipStream_t s);
 hipError_t launch_pose_backward(const int *scene_vert_off, const int *pose_counts, int B, int max_verts,

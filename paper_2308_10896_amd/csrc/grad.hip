@@ -366,8 +366,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                                                   const TriVerts *__restrict__ tv, const float *__restrict__ albedo,
                                                   const float *__restrict__ maps,
                                                   float *__restrict__ gmaps, int i, int j, int tri, const float g[3],
-                                                  int C, float (&vals)[21], float (&accl)[MAXL][22],
-                                                  MapHit (&hits)[MAXL]) {
+                                                  int C, float (&vals)[21], float (&accl)[MAXL][3],
+                                                  MapHit (&hits)[MAXL], const float *__restrict__ jac) {
     const TriVerts r = tv[cv.face_off + tri];
     const float v0[3] = {r.a.x, r.a.y, r.a.z}, v1[3] = {r.a.w, r.b.x, r.b.y}, v2[3] = {r.b.z, r.b.w, r.c.x};
     const float px = ndc_c(i, cv.W), py = -ndc_c(j, cv.H);
@@ -454,13 +454,16 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         const float gndo = ndo > 0.f ? glam : 0.f;
         gn[0] += gndo * ox; gn[1] += gndo * oy; gn[2] += gndo * oz;
         const float gox = gndo * nx, goy = gndo * ny, goz = gndo * nz;
-        float *gl = accl[q];   // M[16], pos[3], dir[3]
+        // this pixel's gradient w.r.t. the light frame (M, pos, dir), pulled
+        // back to the light parameter through the frame's Jacobian at the end
+        float gpos[3] = {0.f, 0.f, 0.f}, gdir[3] = {0.f, 0.f, 0.f};
+        float gcx = 0.f, gcy = 0.f, gcw = 0.f;
         if (l.kind == kDirectional) {
-            gl[19] -= gox; gl[20] -= goy; gl[21] -= goz;
+            gdir[0] -= gox; gdir[1] -= goy; gdir[2] -= goz;
         } else {
             const float od = (ox * gox + oy * goy) + oz * goz;
             const float gpx = (gox - ox * od) / olen, gpy = (goy - oy * od) / olen, gpz = (goz - oz * od) / olen;
-            gl[16] += gpx; gl[17] += gpy; gl[18] += gpz;
+            gpos[0] += gpx; gpos[1] += gpy; gpos[2] += gpz;
             gx[0] -= gpx; gx[1] -= gpy; gx[2] -= gpz;
         }
         if (inside && gvis != 0.f && zz > m1) {
@@ -473,14 +476,14 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             const float gdepth = -gvis * dv_dmu / l.zfar;
             if (l.kind == kDirectional) {
                 gx[0] += gdepth * l.dir[0]; gx[1] += gdepth * l.dir[1]; gx[2] += gdepth * l.dir[2];
-                gl[16] -= gdepth * l.dir[0]; gl[17] -= gdepth * l.dir[1]; gl[18] -= gdepth * l.dir[2];
-                gl[19] += gdepth * (x - l.pos[0]); gl[20] += gdepth * (y - l.pos[1]); gl[21] += gdepth * (z - l.pos[2]);
+                gpos[0] -= gdepth * l.dir[0]; gpos[1] -= gdepth * l.dir[1]; gpos[2] -= gdepth * l.dir[2];
+                gdir[0] += gdepth * (x - l.pos[0]); gdir[1] += gdepth * (y - l.pos[1]); gdir[2] += gdepth * (z - l.pos[2]);
             } else {
                 const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
                 const float dl = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
                 const float ux_ = ddx / dl, uy_ = ddy / dl, uz_ = ddz / dl;
                 gx[0] += gdepth * ux_; gx[1] += gdepth * uy_; gx[2] += gdepth * uz_;
-                gl[16] -= gdepth * ux_; gl[17] -= gdepth * uy_; gl[18] -= gdepth * uz_;
+                gpos[0] -= gdepth * ux_; gpos[1] -= gdepth * uy_; gpos[2] -= gdepth * uz_;
             }
             // bilinear scatter to the moment maps
             if (DIRECT) {
@@ -501,16 +504,23 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             const float gsx = gm1 * dm1fx + gm2 * dm2fx;
             const float gsy = gm1 * dm1fy + gm2 * dm2fy;
             const float hs = 0.5f * S;
-            const float gcx = gsx * hs / cw, gcy = -gsy * hs / cw;
-            const float gcw = (-gsx * hs * cx + gsy * hs * cy) / (cw * cw);
-            const float xh[4] = {x, y, z, 1.f};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                gl[k] += gcx * xh[k];
-                gl[4 + k] += gcy * xh[k];
-                gl[12 + k] += gcw * xh[k];
-            }
+            gcx = gsx * hs / cw;
+            gcy = -gsy * hs / cw;
+            gcw = (-gsx * hs * cx + gsy * hs * cy) / (cw * cw);
             for (int k = 0; k < 3; ++k) gx[k] += (M[k] * gcx + M[4 + k] * gcy) + M[12 + k] * gcw;
+        }
+        // dL/dM = (gcx, gcy, 0, gcw) outer [x, 1]; with dL/dpos, dL/ddir through J
+        const float *J = jac + (size_t)kJac * render_lights[R.light_begin + q];
+        const float xh[4] = {x, y, z, 1.f};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                a += xh[k] * ((gcx * J[3 * k + j] + gcy * J[3 * (4 + k) + j]) + gcw * J[3 * (12 + k) + j]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) a += gpos[i] * J[3 * (16 + i) + j] + gdir[i] * J[3 * (19 + i) + j];
+            accl[q][j] += a;
         }
     }
     // albedo
@@ -605,7 +615,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
     const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
-    float *__restrict__ gtri, float *__restrict__ part_render, int C) {
+    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac) {
     using TS = TileShape<T>;
     const Blk blk = xcd_block2();
     const int cam = blk.y;
@@ -635,11 +645,11 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     for (int rr = cam_renders_off[cam]; rr < cam_renders_off[cam + 1]; ++rr) {
         const int r = cam_renders[rr];
         const RenderConst &R = renders[r];
-        float accl[MAXL][22];
+        float accl[MAXL][3];
 #pragma unroll
         for (int q = 0; q < MAXL; ++q)
 #pragma unroll
-            for (int i = 0; i < 22; ++i) accl[q][i] = 0.f;
+            for (int i = 0; i < 3; ++i) accl[q][i] = 0.f;
         constexpr bool kDirect = TS::PPT * MAXL > 4;     // register budget for deferred map taps
         MapHit hits[TS::PPT][MAXL];
 #pragma unroll
@@ -653,7 +663,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
             if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) continue;
             float tmp[kNV];
             lookup_pixel_grad<MAXL, kDirect>(cv, R, views, render_lights, tv, albedo, maps, gmaps,
-                                             pi[k], pj[k], key[k], g, C, tmp, accl, hits[k]);
+                                             pi[k], pj[k], key[k], g, C, tmp, accl, hits[k], jac);
             act[k] = true;
 #pragma unroll
             for (int i = 0; i < kNV; ++i) val[k][i] += tmp[i];
@@ -673,7 +683,7 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
 #pragma unroll
         for (int q = 0; q < MAXL; ++q) {
             if (q >= R.light_count) break;
-            block_sum_store<TS::NW>(accl[q], part_render + R.part_off + ((long long)q * ntiles + lt) * 22);
+            block_sum_store<TS::NW>(accl[q], part_render + R.part_off + ((long long)q * ntiles + lt) * 3);
         }
     }
     tile_pair_sums<T, kNV>(cv, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
@@ -689,7 +699,7 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
     const unsigned long long *__restrict__ keys, const float *__restrict__ F0, const float *__restrict__ gF1,
     float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
-    float *__restrict__ gtri, float *__restrict__ part_light) {
+    float *__restrict__ gtri, float *__restrict__ part_light, const float *__restrict__ jac) {
     using TS = TileShape<T>;
     const Blk blk = xcd_block2();
     const int lidx = blk.y;
@@ -793,7 +803,17 @@ __global__ __launch_bounds__(256) void light_backward_kernel(
             for (int q = 0; q < 9; ++q) val[k][9 + q] = gc[q];
         }
     }
-    block_sum_store<TS::NW>(accl, part_light + ((long long)l.part_off + lt) * 6);
+    // (pos, dir) terms pulled back to the light parameter
+    const float *J = jac + (size_t)kJac * lidx;
+    float gpar[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        float a = 0.f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) a += accl[i] * J[3 * (16 + i) + j] + accl[3 + i] * J[3 * (19 + i) + j];
+        gpar[j] = a;
+    }
+    block_sum_store<TS::NW>(gpar, part_light + ((long long)l.part_off + lt) * 3);
     tile_pair_sums<T, 18>(l, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(l, key, val, act, matched, gtri);
 }
@@ -864,7 +884,8 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
     const ViewConst *__restrict__ views, int L, const int *__restrict__ scene_vert_off,
     const int *__restrict__ scene_views_off, const int *__restrict__ scene_views, const int *__restrict__ vc_off,
     const int *__restrict__ vc_list, const float *__restrict__ verts, const float *__restrict__ gtri,
-    const float4 *__restrict__ gclip, float *__restrict__ gverts, float *__restrict__ part_gm) {
+    const float4 *__restrict__ gclip, float *__restrict__ gverts, float *__restrict__ part_gm,
+    const float *__restrict__ jac) {
     const int b = blockIdx.y;
     const int nv = scene_vert_off[b + 1] - scene_vert_off[b];
     if ((int)(blockIdx.x * blockDim.x) >= nv) return;        // whole workgroup
@@ -898,16 +919,19 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
 #pragma unroll
         for (int k = 0; k < 3; ++k) gv[k] += (M[k] * gc[0] + M[4 + k] * gc[1]) + M[12 + k] * gc[2];
         if (vi < L) {
+            // dL/dM = (gc_x, gc_y, 0, gc_w) outer [x, 1], pulled back to the light parameter
             const float xh[4] = {x[0], x[1], x[2], in ? 1.f : 0.f};
-            float gm[16];
+            const float *J = jac + (size_t)kJac * vi;
+            float gp[3];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                gm[k] = gc[0] * xh[k];
-                gm[4 + k] = gc[1] * xh[k];
-                gm[8 + k] = 0.f;
-                gm[12 + k] = gc[2] * xh[k];
+            for (int j = 0; j < 3; ++j) {
+                float a = 0.f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    a += xh[k] * ((gc[0] * J[3 * k + j] + gc[1] * J[3 * (4 + k) + j]) + gc[2] * J[3 * (12 + k) + j]);
+                gp[j] = a;
             }
-            block_sum_store<4>(gm, part_gm + ((long long)v.part_gm_off + blockIdx.x) * 16);
+            block_sum_store<4>(gp, part_gm + ((long long)v.part_gm_off + blockIdx.x) * 3);
         }
     }
     if (in)
@@ -940,20 +964,18 @@ __global__ __launch_bounds__(256) void glight_reduce_kernel(const ViewConst *__r
                                                             const float *__restrict__ part_gm,
                                                             const float *__restrict__ part_light,
                                                             const float *__restrict__ part_render,
-                                                            float *__restrict__ glight) {
+                                                            float *__restrict__ gparams) {
     const int l = blockIdx.x;
     const ViewConst &v = views[l];
-    float acc[22];
-#pragma unroll
-    for (int k = 0; k < 22; ++k) acc[k] = 0.f;
+    float acc[3] = {0.f, 0.f, 0.f};
     const int nvb = (v.nverts + 255) / 256;
     for (int q = threadIdx.x; q < nvb; q += blockDim.x)
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc[k] += part_gm[((long long)v.part_gm_off + q) * 16 + k];
+        for (int k = 0; k < 3; ++k) acc[k] += part_gm[((long long)v.part_gm_off + q) * 3 + k];
     const int nlt = v.tiles_x * v.tiles_y;
     for (int q = threadIdx.x; q < nlt; q += blockDim.x)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) acc[16 + k] += part_light[((long long)v.part_off + q) * 6 + k];
+        for (int k = 0; k < 3; ++k) acc[k] += part_light[((long long)v.part_off + q) * 3 + k];
     for (int e = light_renders_off[l]; e < light_renders_off[l + 1]; ++e) {
         const int r = light_renders[e] >> 5, slot = light_renders[e] & 31;
         const RenderConst &R = renders[r];
@@ -961,9 +983,9 @@ __global__ __launch_bounds__(256) void glight_reduce_kernel(const ViewConst *__r
         const int nct = cv.tiles_x * cv.tiles_y;
         for (int q = threadIdx.x; q < nct; q += blockDim.x)
 #pragma unroll
-            for (int k = 0; k < 22; ++k) acc[k] += part_render[R.part_off + ((long long)slot * nct + q) * 22 + k];
+            for (int k = 0; k < 3; ++k) acc[k] += part_render[R.part_off + ((long long)slot * nct + q) * 3 + k];
     }
-    block_sum_store<4>(acc, glight + 24 * l);
+    block_sum_store<4>(acc, gparams + 3 * l);
 }
 
 // ----------------------------------------------------------------------------- pose
@@ -1090,13 +1112,14 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const TriVerts *tv, const unsigned long long *keys, const float *maps,
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
                                   const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
-                                  float *pair_sums, float *gtri, float *part_render, int C, hipStream_t s) {
+                                  float *pair_sums, float *gtri, float *part_render, int C, const float *jac,
+                                  hipStream_t s) {
     if (Cm == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, Cm);
 #define DSM_LB(TT, ML)                                                                                              \
     hipLaunchKernelGGL((lookup_backward_kernel<TT, ML>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,   \
                        cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0,     \
-                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C)
+                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac)
 #define DSM_LB_T(TT)                                                  \
     if (max_lights <= 1) DSM_LB(TT, 1);                               \
     else if (max_lights <= 4) DSM_LB(TT, 4);                          \
@@ -1114,13 +1137,13 @@ hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int ma
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
-                                 hipStream_t s) {
+                                 const float *jac, hipStream_t s) {
     if (L == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, L);
 #define DSM_LIB(TT)                                                                                                  \
     hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, silm,  \
                        verts, tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,     \
-                       part_light)
+                       part_light, jac)
     if (tile == 8) DSM_LIB(8);
     else if (tile == 16) DSM_LIB(16);
     else DSM_LIB(32);
@@ -1134,7 +1157,7 @@ hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max
                                    const int *vc_list, const unsigned *pair_off, const unsigned char *pair_flag,
                                    const float *pair_sums, float *gtri,
                                    unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
-                                   float *gverts, float *part_gm, float *galbedo, int C, hipStream_t s) {
+                                   float *gverts, float *part_gm, float *galbedo, int C, const float *jac, hipStream_t s) {
     if (ntri > 0) {
         hipLaunchKernelGGL(pair_reduce_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
                            pair_flag, pair_sums, gtri, big_list, big_count);
@@ -1145,7 +1168,7 @@ hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max
     if (max_verts > 0)
         hipLaunchKernelGGL(vertex_gather_kernel, dim3((max_verts + 255) / 256, B), dim3(256), 0, s, views, L,
                            scene_vert_off, scene_views_off, scene_views, vc_off, vc_list, verts, gtri, gclip, gverts,
-                           part_gm);
+                           part_gm, jac);
     if (galbedo && max_faces > 0)
         hipLaunchKernelGGL(albedo_gather_kernel, dim3((max_faces + 255) / 256, B), dim3(256), 0, s, views, L,
                            scene_face_off, scene_views_off, scene_views, gtri, galbedo, C);
@@ -1159,10 +1182,10 @@ hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *co
 
 hipError_t launch_glight_reduce(const ViewConst *views, int L, const RenderConst *renders,
                                 const int *light_renders_off, const int *light_renders, const float *part_gm,
-                                const float *part_light, const float *part_render, float *glight, hipStream_t s) {
+                                const float *part_light, const float *part_render, float *gparams, hipStream_t s) {
     if (L == 0) return hipSuccess;
     hipLaunchKernelGGL(glight_reduce_kernel, dim3(L), dim3(256), 0, s, views, renders, light_renders_off,
-                       light_renders, part_gm, part_light, part_render, glight);
+                       light_renders, part_gm, part_light, part_render, gparams);
     return hipGetLastError();
 }
 

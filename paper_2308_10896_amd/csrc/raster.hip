@@ -26,8 +26,13 @@ namespace dsm {
 // ----------------------------------------------------------------------------- light frames
 
 // One thread per light: the light camera from its float32 parameter, in
-// float64, rounded to float32 for the rest of the pipeline.
-__global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L) {
+// float64, rounded to float32 for the rest of the pipeline.  With jac set,
+// also the Jacobian of (M[16], pos[3], dir[3]) with respect to the three
+// parameter components (forward-mode dual numbers), [22][3] per light, used
+// by the reverse pass to pull every light-frame gradient back to the
+// parameter as soon as it is formed.
+__global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L,
+                                    float *jac) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L) return;
     const double p[3] = {params[3 * l], params[3 * l + 1], params[3 * l + 2]};
@@ -39,30 +44,22 @@ __global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, con
         v.pos[i] = (float)pos[i];
         v.dir[i] = (float)dir[i];
     }
-}
-
-// Derivatives of a light frame pulled back to its parameter: glight[l] holds
-// the accumulated gradient w.r.t. (M[16], pos[3], dir[3]).
-__global__ void light_param_grad_kernel(const CamStatic *cams, const float *params, const float *glight,
-                                        float *gparams, int L) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= L) return;
-    Dual3 p[3];
+    if (!jac) return;
+    Dual3 pd[3];
     for (int i = 0; i < 3; ++i) {
-        p[i].v = params[3 * l + i];
-        for (int j = 0; j < 3; ++j) p[i].d[j] = (i == j) ? 1.0 : 0.0;
+        pd[i].v = p[i];
+        for (int j = 0; j < 3; ++j) pd[i].d[j] = (i == j) ? 1.0 : 0.0;
     }
-    Dual3 M[16], pos[3], dir[3];
-    light_frame<Dual3>(cams[l], p, M, pos, dir);
-    const float *g = glight + 24 * l;
-    double out[3] = {0, 0, 0};
+    Dual3 Md[16], posd[3], dird[3];
+    light_frame<Dual3>(cams[l], pd, Md, posd, dird);
+    float *J = jac + (size_t)kJac * l;
     for (int j = 0; j < 3; ++j) {
-        double acc = 0;
-        for (int i = 0; i < 16; ++i) acc += (double)g[i] * M[i].d[j];
-        for (int i = 0; i < 3; ++i) acc += (double)g[16 + i] * pos[i].d[j] + (double)g[19 + i] * dir[i].d[j];
-        out[j] = acc;
+        for (int i = 0; i < 16; ++i) J[3 * i + j] = (float)Md[i].d[j];
+        for (int i = 0; i < 3; ++i) {
+            J[3 * (16 + i) + j] = (float)posd[i].d[j];
+            J[3 * (19 + i) + j] = (float)dird[i].d[j];
+        }
     }
-    for (int j = 0; j < 3; ++j) gparams[3 * l + j] = (float)out[j];
 }
 
 // ----------------------------------------------------------------------------- transform
@@ -571,16 +568,10 @@ __global__ void overflow_count_kernel(DevCounters *counters) {
 
 // ----------------------------------------------------------------------------- host launchers
 
-hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, hipStream_t s) {
+hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
+                               hipStream_t s) {
     if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L);
-    return hipGetLastError();
-}
-
-hipError_t launch_light_param_grad(const CamStatic *cams, const float *params, const float *glight, float *gparams,
-                                   int L, hipStream_t s) {
-    if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(light_param_grad_kernel, dim3((L + 63) / 64), dim3(64), 0, s, cams, params, glight, gparams, L);
+    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L, jac);
     return hipGetLastError();
 }
 
