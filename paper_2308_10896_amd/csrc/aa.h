@@ -121,4 +121,38 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     return true;
 }
 
+// The four neighbours of sample (i, j) (order -x, +x, -y, +y) and which of
+// the pairs can be smoothed at all: different triangles and a front
+// triangle with a silhouette edge in this view.  All neighbour keys are
+// loaded together, then all silhouette bytes, so a sample waits for two
+// dependent loads instead of two per neighbour.  The view must have faces.
+struct AANeighbours {
+    unsigned long long kn[4];
+    int q[4];
+    bool cand[4];
+};
+
+__device__ __forceinline__ AANeighbours aa_neighbours(const ViewConst &v, const unsigned long long *__restrict__ kv,
+                                                      const unsigned char *__restrict__ silm, unsigned long long ks,
+                                                      int i, int j) {
+    AANeighbours n;
+    bool inb[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int in_ = i + (d == 0 ? -1 : d == 1 ? 1 : 0), jn = j + (d == 2 ? -1 : d == 3 ? 1 : 0);
+        inb[d] = in_ >= 0 && in_ < v.W && jn >= 0 && jn < v.H;
+        n.q[d] = inb[d] ? jn * v.W + in_ : j * v.W + i;
+        n.kn[d] = kv[n.q[d]];
+    }
+    unsigned char sil[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const bool differ = inb[d] && (unsigned)n.kn[d] != (unsigned)ks;
+        const unsigned front = ks < n.kn[d] ? (unsigned)ks : (unsigned)n.kn[d];
+        sil[d] = silm[v.setup_off + (differ ? front : 0u)];
+        n.cand[d] = differ && sil[d] != 0;
+    }
+    return n;
+}
+
 }  // namespace dsm

@@ -108,17 +108,17 @@ __global__ __launch_bounds__(256) void aa_camera_backward_kernel(
     const float *g = gimg + R.img_off;
     float acc[3];
     for (int c = 0; c < C; ++c) acc[c] = g[(long long)p * C + c];
-    if (v.antialias) {
+    if (v.antialias && v.nfaces > 0) {
         const int i = p % W, j = p / W;
         const unsigned long long *kv = keys + v.pix_off;
         const unsigned long long ks = kv[p];
         const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+        const AANeighbours nb = aa_neighbours(v, kv, silm, ks, i, j);
         for (int d = 0; d < 4; ++d) {
+            if (!nb.cand[d]) continue;
             const int in_ = i + di[d], jn = j + dj[d];
-            if (in_ < 0 || in_ >= W || jn < 0 || jn >= H) continue;
-            const int q = jn * W + in_;
-            const unsigned long long kn = kv[q];
-            if ((unsigned)kn == (unsigned)ks) continue;
+            const int q = nb.q[d];
+            const unsigned long long kn = nb.kn[d];
             bool self_front;
             AAPair pr;
             if (!aa_eval<true>(v, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;

@@ -105,13 +105,13 @@ __global__ void aa_forward_kernel(const ViewConst *__restrict__ views, const Ren
     for (int c = 0; c < C; ++c) acc[c] = src[base + (long long)p * pstride + c * cstride];
     const float self[3] = {acc[0], C > 1 ? acc[1] : 0.f, C > 2 ? acc[2] : 0.f};
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
-    if (v.antialias) {
+    if (v.antialias && v.nfaces > 0) {
+        const AANeighbours nb = aa_neighbours(v, kv, silm, ks, i, j);
         for (int d = 0; d < 4; ++d) {
+            if (!nb.cand[d]) continue;
             const int in_ = i + di[d], jn = j + dj[d];
-            if (in_ < 0 || in_ >= W || jn < 0 || jn >= H) continue;
-            const int q = jn * W + in_;
-            const unsigned long long kn = kv[q];
-            if ((unsigned)kn == (unsigned)ks) continue;
+            const int q = nb.q[d];
+            const unsigned long long kn = nb.kn[d];
             bool self_front;
             AAPair pr;
             if (!aa_eval<false>(v, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
