@@ -607,7 +607,7 @@ __device__ __forceinline__ void map_window_scatter(const MapHit (&hit)[PPT], int
 }
 
 template <int T, int MAXL>
-__global__ __launch_bounds__(256) void lookup_backward_kernel(
+__device__ __forceinline__ void lookup_backward_body(
     const ViewConst *__restrict__ views, int L, const RenderConst *__restrict__ renders,
     const int *__restrict__ cam_renders_off, const int *__restrict__ cam_renders,
     const int *__restrict__ render_lights, const int *__restrict__ faces, const float *__restrict__ verts,
@@ -688,6 +688,34 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     }
     tile_pair_sums<T, kNV>(cv, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(cv, key, val, act, matched, gtri);
+}
+
+template <int T, int MAXL>
+__global__ __launch_bounds__(256) void lookup_backward_kernel(
+    const ViewConst *__restrict__ views, int L, const RenderConst *__restrict__ renders,
+    const int *__restrict__ cam_renders_off, const int *__restrict__ cam_renders,
+    const int *__restrict__ render_lights, const int *__restrict__ faces, const float *__restrict__ verts,
+    const float *__restrict__ albedo, const TriVerts *__restrict__ tv, const unsigned long long *__restrict__ keys,
+    const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
+    const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
+    const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
+    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac) {
+    lookup_backward_body<T, MAXL>(views, L, renders, cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0, gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac);
+}
+
+// One light per render at 8x8 or 16x16 tiles: capped at 128 VGPRs (4 waves
+// per SIMD instead of 3) at the cost of a few spilled dwords.
+template <int T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void lookup_backward_kernel_1l(
+    const ViewConst *__restrict__ views, int L, const RenderConst *__restrict__ renders,
+    const int *__restrict__ cam_renders_off, const int *__restrict__ cam_renders,
+    const int *__restrict__ render_lights, const int *__restrict__ faces, const float *__restrict__ verts,
+    const float *__restrict__ albedo, const TriVerts *__restrict__ tv, const unsigned long long *__restrict__ keys,
+    const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
+    const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
+    const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
+    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac) {
+    lookup_backward_body<T, 1>(views, L, renders, cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0, gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac);
 }
 
 // ----------------------------------------------------------------------------- light smoothing^T + resolve^T
@@ -1116,12 +1144,17 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   hipStream_t s) {
     if (Cm == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, Cm);
+#define DSM_LB1(TT)                                                                                                 \
+    hipLaunchKernelGGL((lookup_backward_kernel_1l<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,     \
+                       cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0,     \
+                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac)
 #define DSM_LB(TT, ML)                                                                                              \
     hipLaunchKernelGGL((lookup_backward_kernel<TT, ML>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,   \
                        cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0,     \
                        gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac)
 #define DSM_LB_T(TT)                                                  \
-    if (max_lights <= 1) DSM_LB(TT, 1);                               \
+    if (max_lights <= 1 && TT <= 16) DSM_LB1(TT);                     \
+    else if (max_lights <= 1) DSM_LB(TT, 1);                          \
     else if (max_lights <= 4) DSM_LB(TT, 4);                          \
     else DSM_LB(TT, DSM_MAX_LIGHTS_PER_RENDER)
     if (tile == 8) { DSM_LB_T(8); }
@@ -1129,6 +1162,7 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
     else { DSM_LB_T(32); }
 #undef DSM_LB_T
 #undef DSM_LB
+#undef DSM_LB1
     return hipGetLastError();
 }
 

@@ -26,13 +26,8 @@ namespace dsm {
 // ----------------------------------------------------------------------------- light frames
 
 // One thread per light: the light camera from its float32 parameter, in
-// float64, rounded to float32 for the rest of the pipeline.  With jac set,
-// also the Jacobian of (M[16], pos[3], dir[3]) with respect to the three
-// parameter components (forward-mode dual numbers), [22][3] per light, used
-// by the reverse pass to pull every light-frame gradient back to the
-// parameter as soon as it is formed.
-__global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L,
-                                    float *jac) {
+// float64, rounded to float32 for the rest of the pipeline.
+__global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L) return;
     const double p[3] = {params[3 * l], params[3 * l + 1], params[3 * l + 2]};
@@ -44,10 +39,18 @@ __global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, con
         v.pos[i] = (float)pos[i];
         v.dir[i] = (float)dir[i];
     }
-    if (!jac) return;
+}
+
+// The Jacobian of (M[16], pos[3], dir[3]) with respect to the three
+// parameter components (forward-mode dual numbers), [22][3] per light: the
+// reverse pass pulls every light-frame gradient back to the parameter as
+// soon as it is formed.
+__global__ void light_jacobian_kernel(const CamStatic *cams, const float *params, int L, float *jac) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
     Dual3 pd[3];
     for (int i = 0; i < 3; ++i) {
-        pd[i].v = p[i];
+        pd[i].v = params[3 * l + i];
         for (int j = 0; j < 3; ++j) pd[i].d[j] = (i == j) ? 1.0 : 0.0;
     }
     Dual3 Md[16], posd[3], dird[3];
@@ -571,7 +574,8 @@ __global__ void overflow_count_kernel(DevCounters *counters) {
 hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
                                hipStream_t s) {
     if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L, jac);
+    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L);
+    if (jac) hipLaunchKernelGGL(light_jacobian_kernel, dim3((L + 63) / 64), dim3(64), 0, s, cams, params, L, jac);
     return hipGetLastError();
 }
 
