@@ -85,7 +85,7 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVer
 // Light maps: planar 2-channel; grid.y = light view.  Camera images:
 // interleaved C channels; grid.y = render (view = that render's camera).
 template <bool LIGHT>
-__global__ void aa_forward_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void aa_forward_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
                                   const TriSetup *__restrict__ setup, const int *__restrict__ faces,
                                   const unsigned char *__restrict__ silm, const float *__restrict__ verts,
                                   const unsigned long long *__restrict__ keys, const float *__restrict__ src,
