@@ -57,7 +57,8 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     const unsigned t = self_is_front ? ts : tn;
     const int fi = self_is_front ? is : in_, fj = self_is_front ? js : jn;
     const int oi = self_is_front ? in_ : is, oj = self_is_front ? jn : js;
-    if (silm[v.setup_off + t] == 0) return false;   // no silhouette edge to cross
+    const unsigned sm = silm[v.setup_off + t];
+    if (sm == 0) return false;                       // no silhouette edge to cross
     const TriSetup &S = setup[v.setup_off + t];
     const int fX = fi * kSub + kSub / 2, fY = fj * kSub + kSub / 2;
     const int oX = oi * kSub + kSub / 2, oY = oj * kSub + kSub / 2;
@@ -78,7 +79,7 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     const int dX = S.X[b] - S.X[a], dY = S.Y[b] - S.Y[a];
     const bool dir_ok = horiz ? (abs(dY) > abs(dX)) : (abs(dY) <= abs(dX));
     if (!dir_ok) return false;
-    if (!((S.sil >> ebest) & 1)) return false;
+    if (!((sm >> ebest) & 1)) return false;
     const bool sw = S.swapped != 0;
     const int oa = orig_slot(a, sw), ob = orig_slot(b, sw);
     const size_t fidx = (size_t)(v.face_off + (int)t);

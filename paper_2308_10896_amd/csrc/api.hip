@@ -313,6 +313,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_pair_off = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
     p->sc_tile_start = o; o = align_up(o + 4 * ((size_t)tiles + 1));
+    p->sc_facing = o; o = align_up(o + (size_t)tri + 1);
     p->sc_bins = o; o = align_up(o + 4 * (size_t)p->capacity);
     p->sc_bin_pair = o; o = align_up(o + 4 * (size_t)p->capacity);
     p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
@@ -479,8 +480,10 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts, tv,
                              s));
-    DSM_TRY(launch_setup(p->views_d, p->nviews, p->max_faces, p->faces_d, clip, setup, pair_cnt, p->tile, cnt, s));
-    DSM_TRY(launch_silhouettes(p->views_d, p->nviews, p->max_faces, p->adj_d, setup, silm, s));
+    signed char *facing8 = at<signed char>(scratch, p->sc_facing);
+    DSM_TRY(launch_setup(p->views_d, p->nviews, p->max_faces, p->faces_d, clip, setup, facing8, pair_cnt, p->tile,
+                         cnt, s));
+    DSM_TRY(launch_silhouettes(p->views_d, p->nviews, p->max_faces, p->adj_d, facing8, silm, s));
     DSM_MARK(DSM_STAGE_BIN);
     DSM_TRY(launch_scan(pair_cnt, pair_off, scan, p->ntri, s));
     DSM_TRY(launch_binning(p->views_d, setup, pair_off, p->ntri, p->capacity, p->tile, tile_cnt, tile_start,

@@ -60,7 +60,7 @@ struct TriSetup {
     unsigned short bx0, by0, bx1, by1;  // inclusive pixel bbox, clipped to the view
     signed char facing;          // +1 / -1 orientation before re-orienting, 0 if not rasterized
     unsigned char swapped;       // 2nd and 3rd vertex exchanged
-    unsigned char sil;           // bit e: oriented edge e is a silhouette in this view
+    unsigned char sil;           // unused (the silhouette mask lives in its own byte array)
     unsigned char pad1;
     int pad2[2];
 };
@@ -222,10 +222,11 @@ hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const fl
                                hipStream_t s);
 hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
                             hipStream_t s);
-hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj, TriSetup *setup,
-                              unsigned char *silm, hipStream_t s);
+hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj,
+                              const signed char *facing8, unsigned char *silm, hipStream_t s);
 hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const int *faces, const float4 *clip,
-                        TriSetup *setup, unsigned *pair_count, int tile, DevCounters *counters, hipStream_t s);
+                        TriSetup *setup, signed char *facing8, unsigned *pair_count, int tile, DevCounters *counters,
+                        hipStream_t s);
 int scan_scratch_words(int n);
 hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int n, hipStream_t s);
 hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,

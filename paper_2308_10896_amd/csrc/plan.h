@@ -59,7 +59,7 @@ struct dsm_plan {
     // layout of the caller's saved buffer (byte offsets)
     size_t sv_keys = 0, sv_clip = 0, sv_setup = 0, sv_sil = 0, sv_tv = 0, sv_F0 = 0, sv_M = 0, sv_img0 = 0, saved_bytes = 0;
     // layout of the caller's scratch buffer (byte offsets)
-    size_t sc_counters = 0, sc_pair_cnt = 0, sc_pair_off = 0, sc_scan = 0, sc_tile_cnt = 0, sc_tile_start = 0,
+    size_t sc_counters = 0, sc_pair_cnt = 0, sc_pair_off = 0, sc_scan = 0, sc_tile_cnt = 0, sc_tile_start = 0, sc_facing = 0,
            sc_tile_cursor = 0, sc_bins = 0, sc_bin_pair = 0, sc_pair_flag = 0, sc_overflow = 0, sc_F1 = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
            sc_gclip = 0, sc_glight = 0, sc_zero_fwd_end = 0, sc_bigcount = 0, sc_zero_bwd_end = 0,
            sc_pair_sums = 0, sc_gtri = 0, sc_biglist = 0, sc_part_light = 0, sc_part_gm = 0, sc_part_render = 0, sc_jac = 0,

@@ -109,7 +109,8 @@ __device__ __forceinline__ int floor_div256(int a) { return a >= 0 ? (a >> 8) : 
 
 __global__ void setup_kernel(const ViewConst *__restrict__ views, const int *__restrict__ faces,
                              const float4 *__restrict__ clip, TriSetup *__restrict__ setup,
-                             unsigned *__restrict__ pair_count, int tile, DevCounters *counters) {
+                             signed char *__restrict__ facing8, unsigned *__restrict__ pair_count, int tile,
+                             DevCounters *counters) {
     const int view = blockIdx.y;
     const ViewConst &v = views[view];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -170,6 +171,7 @@ __global__ void setup_kernel(const ViewConst *__restrict__ views, const int *__r
     s.by0 = (unsigned short)j0;
     s.by1 = (unsigned short)j1;
     setup[v.setup_off + t] = s;
+    facing8[v.setup_off + t] = s.facing;
     pair_count[v.setup_off + t] = npairs;
     const unsigned long long nc = __popcll(__ballot(!ok && !bad));
     const unsigned long long nb = __popcll(__ballot(bad));
@@ -183,25 +185,24 @@ __global__ void setup_kernel(const ViewConst *__restrict__ views, const int *__r
 // no triangle or more than one other triangle shares it, or when the
 // neighbour across it faces the other way in this view.
 __global__ void silhouette_kernel(const ViewConst *__restrict__ views, const int *__restrict__ adj,
-                                  TriSetup *__restrict__ setup, unsigned char *__restrict__ silm) {
+                                  const signed char *__restrict__ facing8, unsigned char *__restrict__ silm) {
     const ViewConst &v = views[blockIdx.y];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= v.nfaces) return;
-    TriSetup &s = setup[v.setup_off + t];
-    if (s.facing == 0) {
+    const int facing = facing8[v.setup_off + t];
+    if (facing == 0) {
         silm[v.setup_off + t] = 0;
         return;
     }
-    const bool sw = s.swapped != 0;
+    const bool sw = facing < 0;        // second and third vertex were exchanged
     unsigned mask = 0;
     for (int e = 0; e < 3; ++e) {
         const int a = (e + 1) % 3, b = (e + 2) % 3;
         const int oa = sw ? (a == 0 ? 0 : 3 - a) : a, ob = sw ? (b == 0 ? 0 : 3 - b) : b;
         const int nb = adj[3 * (size_t)(v.face_off + t) + (3 - oa - ob)];
-        if (nb < 0 || setup[v.setup_off + nb].facing != s.facing) mask |= 1u << e;
+        if (nb < 0 || facing8[v.setup_off + nb] != facing) mask |= 1u << e;
     }
-    s.sil = (unsigned char)mask;
-    silm[v.setup_off + t] = (unsigned char)mask;   // compact copy for the edge-smoothing passes
+    silm[v.setup_off + t] = (unsigned char)mask;
 }
 
 // ----------------------------------------------------------------------------- scan (exclusive, uint32)
@@ -586,18 +587,19 @@ hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, c
     return hipGetLastError();
 }
 
-hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj, TriSetup *setup,
-                              unsigned char *silm, hipStream_t s) {
+hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj,
+                              const signed char *facing8, unsigned char *silm, hipStream_t s) {
     if (nviews == 0 || max_faces == 0) return hipSuccess;
-    hipLaunchKernelGGL(silhouette_kernel, dim3((max_faces + 255) / 256, nviews), dim3(256), 0, s, views, adj, setup, silm);
+    hipLaunchKernelGGL(silhouette_kernel, dim3((max_faces + 255) / 256, nviews), dim3(256), 0, s, views, adj, facing8, silm);
     return hipGetLastError();
 }
 
 hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const int *faces, const float4 *clip,
-                        TriSetup *setup, unsigned *pair_count, int tile, DevCounters *counters, hipStream_t s) {
+                        TriSetup *setup, signed char *facing8, unsigned *pair_count, int tile, DevCounters *counters,
+                        hipStream_t s) {
     if (nviews == 0 || max_faces == 0) return hipSuccess;
     hipLaunchKernelGGL(setup_kernel, dim3((max_faces + 255) / 256, nviews), dim3(256), 0, s, views, faces, clip,
-                       setup, pair_count, tile, counters);
+                       setup, facing8, pair_count, tile, counters);
     return hipGetLastError();
 }
 
