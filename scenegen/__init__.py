@@ -423,3 +423,38 @@ CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
 def random_image_grad(shape, seed):
     """Seeded upstream gradient for backward-only tests."""
     return f32(np.random.default_rng(seed).standard_normal(shape))
+
+
+def grid_quad(half: float, y: float, n: int):
+    """Horizontal square [-half, half]^2 at height y as an n x n grid of quads (normal +y)."""
+    t = np.linspace(-half, half, n + 1)
+    v = np.array([[x, y, z] for z in t for x in t], np.float64)
+    f = []
+    for r in range(n):
+        for c in range(n):
+            a, b = r * (n + 1) + c, r * (n + 1) + c + 1
+            d, e = a + (n + 1), b + (n + 1)
+            f += [(a, d, e), (a, e, b)]
+    return f32(v), np.array(f, np.int32)
+
+
+def minimal_plane(k: int = 5, antialias: bool = True, filter: str = 'box', resolution: int = 256,
+                  view: int = 128, occluder_tess: int = 1, offset=(0.0, 0.0, 0.0)) -> Batch:
+    """The "minimal plane" setup of the convergence experiments (supplementary,
+    experiment details): a square occluder (half-size 0.25 at y = 0.5) over a
+    parallel square receiver (half-size 0.75 at y = 0), a directional light
+    travelling straight down, and a camera between the two looking down at
+    the receiver, so that the images show only the shadow.  The occluder's
+    vertices come first and follow the scene pose (translation `offset`
+    relative to the reference, which is pose zero)."""
+    ov, of = grid_quad(0.25, 0.0, occluder_tess)     # object space, centre (0, 0.5, 0)
+    rv, rf = quad(0.75, 0.0)
+    v, f = merge([(ov, of), (rv, rf)])
+    sc = Scene(verts=v, faces=f, albedo=np.full((len(f), 1), 0.8, np.float32), pose_count=len(ov),
+               pose_center=f32([0, 0.5, 0]), pose=f32([0, 0, 0, *offset]))
+    light = Light('directional', f32([0, -1, 0]), resolution=resolution, filter=filter, k=k,
+                  up=f32([0, 0, 1]), ortho_half=1.0, antialias=antialias)
+    cam = Camera(eye=f32([0, 0.45, 0]), target=f32([0, 0, 0]), fov_deg=120.0, width=view, height=view,
+                 up=f32([0, 0, -1]))
+    return Batch('minimal-plane', [sc], [light], [cam], [Render(0, [0])], channels=1,
+                 target_poses=[np.zeros(6, np.float32)])
