@@ -13,6 +13,7 @@ from oracle import pipeline as P
 # variance floor).  Gradients: normwise per parameter group.
 MAP_RTOL, MAP_ATOL = 1e-4, 1e-6
 IMG_RTOL, IMG_ATOL = 1e-4, 1e-4
+GRAD_TOL = 1e-3      # normwise relative, per parameter group
 
 
 def gpu_run(batch, tile_size=0, bin_scale=0, grad_images=None, pose=False):

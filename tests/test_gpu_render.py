@@ -83,7 +83,7 @@ def test_run_twice_bit_identical_forward():
         assert np.array_equal(x, y)
 
 
-GRAD_TOL = 1e-3
+from parity_helpers import GRAD_TOL  # noqa: E402
 
 
 @pytest.mark.parametrize('name', ['cfg0', 'cfg0_ragged', 'cfg1_small'])
