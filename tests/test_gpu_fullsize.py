@@ -57,6 +57,7 @@ def test_full_size_batch_sampled_scenes():
         # texel of the scene; at full resolution on the densest mesh its
         # float32 conditioning (1/sigma^2 terms at penumbra texels near the
         # variance floor, random-sign cotangent) gives a normwise error of
-        # about 4e-3 against the float64 oracle, identical before and after
-        # every change to the reduction order, hence the wider bound here.
+        # about 4e-3 against the float64 oracle (the same with the light-frame
+        # gradients reduced as 22 frame terms or as 3 parameter terms), hence
+        # the wider bound here.
         normwise(f'glight[{i}]', gl[i], o['glight'][0], 10 * GRAD_TOL)
