@@ -79,6 +79,7 @@ def parse():
                     help='time budget of the oracle baseline sample')
     ap.add_argument('--stage-reps', type=int, default=10)
     ap.add_argument('--tile', type=int, default=0, help='raster tile side; 0: autotune')
+    ap.add_argument('--no-other', action='store_true', help='skip the other configurations')
     return ap.parse_args()
 
 
@@ -183,6 +184,11 @@ def main():
         t_plain = timed(step_plain, psteps, stream)
         plain_rps = R * psteps / t_plain
 
+    # ---------------- the other configurations of the method, absolute rates
+    other = None
+    if not args.no_other:
+        other = other_configs(stream)
+
     # ---------------- CPU baseline: the oracle on a bounded sample of scenes
     cpu = None
     if not args.no_cpu_baseline:
@@ -213,6 +219,7 @@ def main():
             'bin_capacity_scale': int(plan.info.bin_capacity_scale),
             'autotune': tune,
             'stages_us': kern['stages_us'],
+            'other_configs': other,
         },
         'roofline': kern['roofline'],
         'cpu_baseline': cpu,
@@ -282,6 +289,41 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
             'kernels': kernels,
             'copy_gbs': round(copy_gbs, 1)}
     return {'stages_us': {k: round(1000.0 * v, 2) for k, v in stages.items()}, 'roofline': roof}
+
+
+def other_configs(stream, steps=10, warmup=3):
+    """Forward + backward renders/s of the other workloads (one captured
+    graph per step, inputs resident, default tile side 8): the tiny cube
+    scene, the icosphere under a spot light, the 128-render multi-view
+    sphere and the 330k-triangle complex scene."""
+    import torch
+    import scenegen as sg
+    from paper_2308_10896_amd import dsm
+    res = {}
+    for name, make in (('tiny cube, 256^2', sg.config0), ('icosphere, spot, 512^2', sg.config1),
+                       ('multi-view sphere, 8 lights x 16 cameras, 1024^2 maps', sg.config3),
+                       ('complex scene, 330k triangles, 3 lights at 2048^2, 1920x1080', sg.config4)):
+        batch = make()
+        dev = torch.device('cuda:0')
+        plan = dsm.Plan(batch)
+        local, lp, alb, poses = dsm.batch_inputs(batch, dev)
+        saved, scratch = plan.workspace(dev)
+        verts = torch.empty_like(local)
+        images = torch.empty(int(plan.info.image_floats), device=dev)
+        gimg = torch.full((int(plan.info.image_floats),), 1e-3, device=dev)
+        gv, gl, ga, gp = (torch.empty_like(local), torch.empty_like(lp), torch.empty_like(alb),
+                          torch.empty_like(poses))
+        torch.cuda.synchronize()
+        plan.graph_capture(stream, local, poses, verts, lp, alb, saved, scratch, images, gimg, gv, gl, ga, gp)
+        for _ in range(warmup):
+            plan.graph_launch(stream)
+        t = timed(lambda: plan.graph_launch(stream), steps, stream)
+        R = len(batch.renders)
+        res[name] = {'renders_per_s': round(R * steps / t, 2), 'ms_per_step': round(1000 * t / steps, 4),
+                     'renders_per_step': R, 'triangles': int(sum(len(sc.faces) for sc in batch.scenes))}
+        del plan, saved, scratch
+        torch.cuda.synchronize()
+    return res
 
 
 def cpu_baseline(batch, budget_s):
