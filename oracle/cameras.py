@@ -7,6 +7,13 @@ outside the scene facing the origin; a spot light uses a perspective camera at
 its position with a configurable field of view.  A point light here uses the
 same perspective construction (one shadow map per light, Sec. 5).
 
+An omnidirectional point light is parameterized over several planes arranged
+as a box around it, as Sec. 3 allows when one plane does not cover every ray
+(Sec. 5 names this route): six "cube-face" lights share the position, face
+f = 2a + s looking along +e_a (s = 0) or -e_a (s = 1) through a square 90
+degree frustum, and face f shades exactly the points whose direction from
+the light has dominant axis a with sign s (ties to the lower axis).
+
 Matrices are textbook OpenGL-style (right-handed, camera looking down -z,
 clip -> NDC in [-1,1]^3).  The matrix the discrete raster uses is the float32
 rounding of the float64 matrix; the continuous part uses the same rounded
@@ -82,14 +89,30 @@ def camera_matrix(cam):
     return round_f32(P @ V)
 
 
+# viewing direction and up vector of cube face f = 2a + s
+CUBE_AXES = ((1.0, 0.0, 0.0), (-1.0, 0.0, 0.0), (0.0, 1.0, 0.0),
+             (0.0, -1.0, 0.0), (0.0, 0.0, 1.0), (0.0, 0.0, -1.0))
+CUBE_UPS = ((0.0, 1.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0),
+            (0.0, 0.0, 1.0), (0.0, 1.0, 0.0), (0.0, 1.0, 0.0))
+
+
+def cube_face_of(d):
+    """Cube face owning each direction d (n, 3): the axis of largest |d_a|
+    (the first one on ties), and its sign (d_a < 0 -> the odd face)."""
+    d = np.asarray(d, np.float64)
+    a = np.argmax(np.abs(d), axis=1)
+    neg = d[np.arange(len(d)), a] < 0
+    return 2 * a + neg.astype(np.int64)
+
+
 def light_frame(light, param):
     """Light camera and the quantities the lookup needs, from the light's
     differentiable parameter (position, or travel direction for directional).
 
     Returns dict with M (4x4 view-projection), pos (point/spot: position;
     directional: camera eye on the plane distances are measured from), w
-    (directional: unit travel direction; spot: cone axis), far, kind,
-    cos_half (spot cone)."""
+    (directional: unit travel direction; spot: cone axis; cube face: face
+    axis), far, kind, cos_half (spot cone), face (cube face index)."""
     if light.kind == 'directional':
         w = normalize(param)
         eye = -light.dir_distance * w
@@ -97,6 +120,12 @@ def light_frame(light, param):
         P = orthographic(light.ortho_half, light.near, light.far)
         return dict(M=round_f32(P @ V), pos=round_f32(eye), w=round_f32(w), far=light.far,
                     kind='directional', cos_half=None)
+    if light.kind == 'cubeface':
+        axis = _t(CUBE_AXES[light.face])
+        V = look_at(param, param + axis, _t(CUBE_UPS[light.face]))
+        P = perspective(90.0, 1.0, light.near, light.far)
+        return dict(M=round_f32(P @ V), pos=param, w=axis, far=light.far, kind='cubeface',
+                    cos_half=None, face=light.face)
     tgt = _t(light.target)
     V = look_at(param, tgt, _t(light.up))
     P = perspective(light.fov_deg, 1.0, light.near, light.far)

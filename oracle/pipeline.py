@@ -17,6 +17,8 @@ details; Alg. 2, ComputeVisibility):
   * mu = m1, sigma^2 = max(m2 - m1^2, eps); v = 1 if d <= mu, else
     sigma^2 / (sigma^2 + (d - mu)^2) (Sec. 3, one-sided Chebyshev bound);
   * colour = sum over lights of albedo * max(0, n . omega) * v * I * cone;
+    cone is the hard mask of a spot light's cone, or of the directions a
+    cube face owns (1 for directional and point lights);
   * the same border smoothing is applied to the shaded image.
 Loss: mean squared error to a target image.
 """
@@ -282,6 +284,13 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
                 cosang = (cameras.normalize(x - fr['pos']) * fr['w']).sum(1).detach()
                 cone = (cosang >= fr['cos_half']).to(D)
                 margin = (cosang - fr['cos_half']).abs()
+            elif fr['kind'] == 'cubeface':
+                dv = (x - fr['pos']).detach().numpy()
+                cone = torch.as_tensor(cameras.cube_face_of(dv) == fr['face']).to(D)
+                # relative gap between the two largest |d_a|: the face choice
+                # (and the frustum border) is ambiguous where it vanishes
+                ad = np.sort(np.abs(dv), axis=1)
+                margin = torch.as_tensor((ad[:, 2] - ad[:, 1]) / np.maximum(ad[:, 2], 1e-30))
             col = col + rho * (lam * vis * L.intensity * cone)[:, None]
             fl_flags[li] = dict(inside=inside.numpy(), lit_side=(ndl > 0).detach().numpy(),
                                 branch=(z <= m[:, 0]).detach().numpy(),

@@ -48,7 +48,7 @@ class Scene:
 
 @dataclass
 class Light:
-    kind: str                    # 'directional' | 'point' | 'spot'
+    kind: str                    # 'directional' | 'point' | 'spot' | 'cubeface'
     param: np.ndarray            # (3,) float32: position, or travel direction for directional
     scene: int = 0
     target: np.ndarray = field(default_factory=lambda: np.zeros(3, np.float32))
@@ -65,6 +65,7 @@ class Light:
     ortho_half: float = ORTHO_HALF
     min_variance: float = MIN_VARIANCE
     antialias: bool = True
+    face: int = 0                # 'cubeface': face index 0..5 (+x, -x, +y, -y, +z, -z)
 
 
 @dataclass
@@ -458,3 +459,38 @@ def minimal_plane(k: int = 5, antialias: bool = True, filter: str = 'box', resol
                  up=f32([0, 0, -1]))
     return Batch('minimal-plane', [sc], [light], [cam], [Render(0, [0])], channels=1,
                  target_poses=[np.zeros(6, np.float32)])
+
+
+def cube_lights(position, scene: int = 0, resolution: int = 256, **kw) -> List[Light]:
+    """The six cube-face lights of one omnidirectional point light at
+    `position` (faces +x, -x, +y, -y, +z, -z); each keeps its own parameter,
+    so the gradient for the shared position is the sum over the six."""
+    p = f32(position)
+    return [Light('cubeface', p.copy(), scene=scene, resolution=resolution, fov_deg=90.0, face=f, **kw)
+            for f in range(6)]
+
+
+# occluder centres and radii of the cube-light scene: one below the light, one
+# towards +x, one towards -z and one on the -x / +z face seam
+CUBE_SCENE_OCCLUDERS = (((0.15, 0.3, 0.1), 0.08), ((0.7, 0.35, 0.1), 0.1),
+                        ((-0.1, 0.3, -0.6), 0.1), ((-0.45, 0.3, 0.45), 0.1))
+
+
+def cube_light_scene(resolution: int = 128, view: int = 128, k: int = 5, antialias: bool = True,
+                     light_pos=(0.03, 0.6, -0.02), ground_n: int = 16, sphere_subdiv: int = 2) -> Batch:
+    """An omnidirectional point light low over a tessellated ground (half-size
+    2 at y = 0) with four small icospheres around it whose shadows fall
+    through different faces of the light's cube (below, +x, -z and across the
+    -x / +z seam); nothing lies above the light, so the +y face sees an empty
+    view.  One camera looks down at the ground from above and in front."""
+    parts = [grid_quad(2.0, 0.0, ground_n)]
+    for c, r in CUBE_SCENE_OCCLUDERS:
+        sv, sf = icosphere(sphere_subdiv)
+        parts.append((sv * r + np.asarray(c, np.float64), sf))
+    v, f = merge(parts)
+    sc = Scene(verts=v, faces=f, albedo=np.full((len(f), 1), 0.8, np.float32))
+    lights = cube_lights(light_pos, resolution=resolution, k=k, antialias=antialias)
+    cam = Camera(eye=f32([0, 3.2, 2.6]), target=f32([0, 0, 0]), fov_deg=60.0, width=view, height=view)
+    tgt = f32(np.asarray(light_pos, np.float64) + [0.08, 0.0, 0.05])
+    return Batch('cube-light', [sc], lights, [cam], [Render(0, list(range(6)))], channels=1,
+                 target_light_params=[tgt.copy() for _ in range(6)])
