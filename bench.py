@@ -39,14 +39,14 @@ HBM_PEAK_GBS = 8000.0
 PMC_FETCH_SCALE = 131072.0 / 65548.0
 PMC_WRITE_SCALE = 131072.0 / 131072.0
 PMC_TRAFFIC = {
-    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65882.8, write_kib=131072.0,
-                   sources=('blur.hip', 'dsm_internal.h'), sha1='56979c1b3c0f97dd'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65692.2, write_kib=131072.0,
-                       sources=('blur.hip', 'dsm_internal.h'), sha1='56979c1b3c0f97dd'),
+    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65870.4, write_kib=131072.0,
+                   sources=('blur.hip', 'dsm_internal.h'), sha1='423ba4e68940a69d'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65699.0, write_kib=131072.0,
+                       sources=('blur.hip', 'dsm_internal.h'), sha1='423ba4e68940a69d'),
     'lookup': dict(kernel='lookup_kernel', fetch_kib=158527.9, write_kib=65536.0,
-                   sources=('shade.hip', 'dsm_internal.h'), sha1='b02fb41723e66ce8'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel<8, 1>', fetch_kib=119337.2, write_kib=108520.3,
-                       sources=('grad.hip', 'dsm_internal.h'), sha1='bcb1ef7c5f4b51e4'),
+                   sources=('shade.hip', 'dsm_internal.h'), sha1='4a56b742b5b58d17'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=119871.4, write_kib=90773.0,
+                       sources=('grad.hip', 'dsm_internal.h'), sha1='5da2a0d44befeef2'),
 }
 
 
