@@ -15,7 +15,9 @@ degree frustum, and face f shades exactly the points whose direction from
 the light has dominant axis a with sign s (ties to the lower axis).
 
 Matrices are textbook OpenGL-style (right-handed, camera looking down -z,
-clip -> NDC in [-1,1]^3).  The matrix the discrete raster uses is the float32
+clip -> NDC in [-1,1]^3).  Camera settings (field of view, near and far
+planes, orthographic extent, eye distance) enter as the float32 values a
+scene description holds, like every other scene input.  The matrix the discrete raster uses is the float32
 rounding of the float64 matrix; the continuous part uses the same rounded
 values while autograd differentiates the float64 construction
 ("straight-through" rounding), so both parts see one light camera.
@@ -52,6 +54,11 @@ def look_at(eye, target, up):
     ])
 
 
+def f32(x):
+    """A scalar camera setting as the float32 value the scene description holds."""
+    return float(np.float32(x))
+
+
 def perspective(fov_deg, aspect, near, far):
     t = 1.0 / math.tan(math.radians(fov_deg) / 2.0)
     return _t([[t / aspect, 0, 0, 0],
@@ -85,7 +92,7 @@ def round_f32(x):
 def camera_matrix(cam):
     """Viewer camera VP (float64), aspect = width / height."""
     V = look_at(_t(cam.eye), _t(cam.target), _t(cam.up))
-    P = perspective(cam.fov_deg, cam.width / cam.height, cam.near, cam.far)
+    P = perspective(f32(cam.fov_deg), cam.width / cam.height, f32(cam.near), f32(cam.far))
     return round_f32(P @ V)
 
 
@@ -115,21 +122,21 @@ def light_frame(light, param):
     axis), far, kind, cos_half (spot cone), face (cube face index)."""
     if light.kind == 'directional':
         w = normalize(param)
-        eye = -light.dir_distance * w
+        eye = -f32(light.dir_distance) * w
         V = look_at(eye, torch.zeros(3, dtype=D), _t(light.up))
-        P = orthographic(light.ortho_half, light.near, light.far)
-        return dict(M=round_f32(P @ V), pos=round_f32(eye), w=round_f32(w), far=light.far,
+        P = orthographic(f32(light.ortho_half), f32(light.near), f32(light.far))
+        return dict(M=round_f32(P @ V), pos=round_f32(eye), w=round_f32(w), far=f32(light.far),
                     kind='directional', cos_half=None)
     if light.kind == 'cubeface':
         axis = _t(CUBE_AXES[light.face])
         V = look_at(param, param + axis, _t(CUBE_UPS[light.face]))
-        P = perspective(90.0, 1.0, light.near, light.far)
-        return dict(M=round_f32(P @ V), pos=param, w=axis, far=light.far, kind='cubeface',
+        P = perspective(90.0, 1.0, f32(light.near), f32(light.far))
+        return dict(M=round_f32(P @ V), pos=param, w=axis, far=f32(light.far), kind='cubeface',
                     cos_half=None, face=light.face)
     tgt = _t(light.target)
     V = look_at(param, tgt, _t(light.up))
-    P = perspective(light.fov_deg, 1.0, light.near, light.far)
+    P = perspective(f32(light.fov_deg), 1.0, f32(light.near), f32(light.far))
     axis = normalize(tgt - param)
     cos_half = math.cos(math.radians(light.fov_deg) / 2.0) if light.kind == 'spot' else None
-    return dict(M=round_f32(P @ V), pos=param, w=round_f32(axis), far=light.far, kind=light.kind,
+    return dict(M=round_f32(P @ V), pos=param, w=round_f32(axis), far=f32(light.far), kind=light.kind,
                 cos_half=cos_half)

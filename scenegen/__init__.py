@@ -491,6 +491,6 @@ def cube_light_scene(resolution: int = 128, view: int = 128, k: int = 5, antiali
     sc = Scene(verts=v, faces=f, albedo=np.full((len(f), 1), 0.8, np.float32))
     lights = cube_lights(light_pos, resolution=resolution, k=k, antialias=antialias)
     cam = Camera(eye=f32([0, 3.2, 2.6]), target=f32([0, 0, 0]), fov_deg=60.0, width=view, height=view)
-    tgt = f32(np.asarray(light_pos, np.float64) + [0.08, 0.0, 0.05])
+    tgt = f32(np.asarray(light_pos, np.float64) + [0.0713, 0.0, 0.0437])
     return Batch('cube-light', [sc], lights, [cam], [Render(0, list(range(6)))], channels=1,
                  target_light_params=[tgt.copy() for _ in range(6)])
