@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DSM_ABI_VERSION 1
+#define DSM_ABI_VERSION 2
 
 typedef enum {
     DSM_OK = 0,
@@ -51,7 +51,7 @@ typedef enum {
     DSM_ERR_DEVICE_FAULT = 7          /* device-side invariant violated (see dsm_get_stats) */
 } dsm_status;
 
-enum { DSM_LIGHT_DIRECTIONAL = 0, DSM_LIGHT_POINT = 1, DSM_LIGHT_SPOT = 2 };
+enum { DSM_LIGHT_DIRECTIONAL = 0, DSM_LIGHT_POINT = 1, DSM_LIGHT_SPOT = 2, DSM_LIGHT_CUBE_FACE = 3 };
 enum { DSM_FILTER_BOX = 0, DSM_FILTER_GAUSSIAN = 1 };
 
 /* Limits checked by every entry point. */
@@ -74,6 +74,21 @@ typedef struct dsm_plan dsm_plan;
  *                field of view fov_deg, aspect 1; d(x) = |x - position|.
  *                A spot light lights only the cone of half-angle fov_deg/2
  *                around its axis (hard mask, no gradient through it).
+ *   cube face:   one of the six faces of an omnidirectional point light's
+ *                cube shadow map (Sec. 3: rays parameterized over several
+ *                planes arranged as a box; Sec. 5: omnidirectional lights
+ *                by several shadow maps).  Face f = cube_face in 0..5
+ *                looks along +x, -x, +y, -y, +z, -z from the position
+ *                through a square 90 degree frustum (target, up and fov_deg
+ *                are ignored; the library picks the face's up vector), and
+ *                lights only the points x whose direction x - position has
+ *                its largest |component| on the face's axis with the face's
+ *                sign (ties go to the lower axis; hard mask, no gradient
+ *                through it), so six faces with one position light every
+ *                direction exactly once.  Each face is a light of its own
+ *                with its own map and parameter slot; the gradient for the
+ *                shared position is the sum of the six.  Seams are filtered
+ *                and fetched per face with clamp-to-edge.
  * Depths are stored as z = d / zfar.  `k` is the odd filter size of the
  * moment filter (box or Gaussian with std. dev. sigma in texels; sigma <= 0
  * means (k-1)/3).  min_variance floors sigma^2 = m2 - m1^2.
@@ -94,6 +109,7 @@ typedef struct {
     float sigma;
     float min_variance;
     int32_t antialias;     /* smooth the light view at primitive borders    */
+    int32_t cube_face;     /* DSM_LIGHT_CUBE_FACE: face 0..5; else ignored  */
 } dsm_light_desc;
 
 /* A perspective viewer camera (fixed; no gradient). */

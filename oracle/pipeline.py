@@ -297,6 +297,8 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
                                 clamp=(m[:, 1] - m[:, 0] ** 2 < L.min_variance).detach().numpy(),
                                 floor=np.stack([torch.floor(sx).detach().numpy(),
                                                 torch.floor(sy).detach().numpy()]),
+                                frac=np.stack([(sx - torch.floor(sx)).detach().numpy(),
+                                               (sy - torch.floor(sy)).detach().numpy()]),
                                 cone_margin=None if margin is None else margin.numpy())
         img0 = torch.zeros(W * H, batch.channels, dtype=D)
         img0 = img0.index_put((torch.as_tensor(flat),), col)

@@ -15,7 +15,7 @@ DSM_OK = 0
 STATUS = {0: 'ok', 1: 'invalid argument', 2: 'out of memory', 3: 'workspace too small', 4: 'unsupported',
           5: 'no device', 6: 'HIP error', 7: 'device fault'}
 
-LIGHT_TYPES = {'directional': 0, 'point': 1, 'spot': 2}
+LIGHT_TYPES = {'directional': 0, 'point': 1, 'spot': 2, 'cubeface': 3}
 FILTERS = {'box': 0, 'gaussian': 1}
 
 
@@ -30,7 +30,7 @@ class LightDesc(C.Structure):
                 ('fov_deg', C.c_float), ('dir_distance', C.c_float), ('ortho_half', C.c_float),
                 ('znear', C.c_float), ('zfar', C.c_float), ('intensity', C.c_float),
                 ('resolution', C.c_int32), ('filter', C.c_int32), ('k', C.c_int32), ('sigma', C.c_float),
-                ('min_variance', C.c_float), ('antialias', C.c_int32)]
+                ('min_variance', C.c_float), ('antialias', C.c_int32), ('cube_face', C.c_int32)]
 
 
 class CameraDesc(C.Structure):

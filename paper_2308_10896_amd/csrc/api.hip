@@ -99,11 +99,13 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     }
     for (int l = 0; l < L; ++l) {
         const dsm_light_desc &x = d->lights[l];
-        if (x.type < 0 || x.type > 2 || x.scene < 0 || x.scene >= B) return DSM_ERR_INVALID_ARG;
+        if (x.type < 0 || x.type > DSM_LIGHT_CUBE_FACE || x.scene < 0 || x.scene >= B) return DSM_ERR_INVALID_ARG;
+        if (x.type == DSM_LIGHT_CUBE_FACE && (x.cube_face < 0 || x.cube_face > 5)) return DSM_ERR_INVALID_ARG;
         if (!valid_filter(x.resolution, x.filter, x.k)) return DSM_ERR_INVALID_ARG;
         if (!(x.znear > 0 && x.zfar > x.znear) || !std::isfinite(x.zfar)) return DSM_ERR_INVALID_ARG;
         if (x.type == DSM_LIGHT_DIRECTIONAL && !(x.ortho_half > 0 && x.dir_distance > 0)) return DSM_ERR_INVALID_ARG;
-        if (x.type != DSM_LIGHT_DIRECTIONAL && !(x.fov_deg > 0 && x.fov_deg < 180)) return DSM_ERR_INVALID_ARG;
+        if ((x.type == DSM_LIGHT_POINT || x.type == DSM_LIGHT_SPOT) && !(x.fov_deg > 0 && x.fov_deg < 180))
+            return DSM_ERR_INVALID_ARG;
         if (!finite3(x.target) || !finite3(x.up) || !(x.min_variance >= 0) || !std::isfinite(x.intensity))
             return DSM_ERR_INVALID_ARG;
     }
@@ -178,7 +180,11 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         const dsm_light_desc &x = d->lights[l];
         ViewConst v;
         memset(&v, 0, sizeof(v));
-        v.kind = x.type == DSM_LIGHT_DIRECTIONAL ? kDirectional : (x.type == DSM_LIGHT_POINT ? kPoint : kSpot);
+        v.kind = x.type == DSM_LIGHT_DIRECTIONAL ? kDirectional
+                 : x.type == DSM_LIGHT_POINT   ? kPoint
+                 : x.type == DSM_LIGHT_SPOT    ? kSpot
+                                               : kCubeFace;
+        v.cube_face = v.kind == kCubeFace ? x.cube_face : 0;
         v.zfar = x.zfar;
         v.cos_half = (float)cos((double)x.fov_deg * (M_PI / 180.0) / 2.0);
         v.intensity = x.intensity;
@@ -199,6 +205,15 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         cs.kind = v.kind;
         for (int i = 0; i < 3; ++i) { cs.target[i] = x.target[i]; cs.up[i] = x.up[i]; }
         cs.focal = 1.0 / tan((double)x.fov_deg * (M_PI / 180.0) / 2.0);
+        if (v.kind == kCubeFace) {
+            // face f = 2a + s views along (-1)^s e_a; up is +z for the y faces, +y otherwise
+            const int a = x.cube_face >> 1;
+            for (int i = 0; i < 3; ++i) {
+                cs.target[i] = i == a ? ((x.cube_face & 1) ? -1.0 : 1.0) : 0.0;
+                cs.up[i] = i == (a == 1 ? 2 : 1) ? 1.0 : 0.0;
+            }
+            cs.focal = 1.0;
+        }
         cs.aspect = 1.0;
         cs.znear = x.znear;
         cs.zfar = x.zfar;

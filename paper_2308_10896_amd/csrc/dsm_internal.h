@@ -14,7 +14,7 @@ constexpr float kGuard = 32768.0f;     // |screen coordinate| limit in pixels
 constexpr uint64_t kBgKey = ~0ull;     // background key (no triangle)
 constexpr int kMaxTaps = 32;
 
-enum ViewKind { kDirectional = 0, kPoint = 1, kSpot = 2, kCamera = 3 };
+enum ViewKind { kDirectional = 0, kPoint = 1, kSpot = 2, kCamera = 3, kCubeFace = 4 };
 
 // One view: a light camera (views [0, L)) or a viewer camera (views [L, L+Cm)).
 // Light views get M / pos / dir rewritten on the device by every forward.
@@ -40,7 +40,20 @@ struct ViewConst {
     long long map_off;  // light views: first texel of the 2-channel maps (plane stride S*S)
     int part_off;       // light views: first per-tile slot of the backward light-frame partials
     int part_gm_off;    // light views: first per-vertex-block slot of the dL/dM partials
+    int cube_face;      // cube-face lights: face 0..5 (+x, -x, +y, -y, +z, -z)
 };
+
+// Cube face owning the direction d from an omnidirectional light: the axis of
+// the largest |d_a| (the first one on ties) and its sign, face 2a (+) or
+// 2a + 1 (-).
+__device__ __forceinline__ int cube_face_of(float dx, float dy, float dz) {
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int a = 0;
+    float m = ax, s = dx;
+    if (ay > m) { a = 1; m = ay; s = dy; }
+    if (az > m) { a = 2; s = dz; }
+    return 2 * a + (s < 0.f ? 1 : 0);
+}
 
 struct RenderConst {
     int camera_view;    // view index of the camera

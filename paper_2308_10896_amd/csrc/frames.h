@@ -78,7 +78,7 @@ __host__ __device__ inline Vec3<T> unit3(const Vec3<T> &a) {
 // Static description of a camera (viewer or light), float64 on the host.
 struct CamStatic {
     int kind;              // ViewKind
-    double target[3], up[3];
+    double target[3], up[3];  // cube faces: target holds the face axis
     double focal;          // 1 / tan(fov/2), perspective
     double aspect;         // width / height
     double znear, zfar;
@@ -138,7 +138,11 @@ __host__ __device__ inline void light_frame(const CamStatic &c, const T p[3], T 
         pos[0] = eye.x; pos[1] = eye.y; pos[2] = eye.z;
         dir[0] = w.x; dir[1] = w.y; dir[2] = w.z;
     } else {
-        const Vec3<T> tg{mkT<T>(c.target[0]), mkT<T>(c.target[1]), mkT<T>(c.target[2])};
+        // cube faces keep their viewing axis in `target`: the camera looks
+        // from the position along that fixed axis
+        const Vec3<T> tg = c.kind == 4
+            ? Vec3<T>{P3.x + mkT<T>(c.target[0]), P3.y + mkT<T>(c.target[1]), P3.z + mkT<T>(c.target[2])}
+            : Vec3<T>{mkT<T>(c.target[0]), mkT<T>(c.target[1]), mkT<T>(c.target[2])};
         view_projection(c, P3, tg, M);
         const Vec3<T> ax = unit3(sub3(tg, P3));
         pos[0] = P3.x; pos[1] = P3.y; pos[2] = P3.z;

@@ -403,6 +403,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         int ixs = 0, iys = 0;
         hits[q].gm1 = 0.f;
         hits[q].gm2 = 0.f;
+        // outside its own directions a cube face adds nothing, nor any gradient
+        if (l.kind == kCubeFace && cube_face_of(x - l.pos[0], y - l.pos[1], z - l.pos[2]) != l.cube_face) continue;
         const int S = l.W;
         const float *ma = maps + l.map_off, *mb = maps + l.map_off + (long long)S * S;
         if (inside) {

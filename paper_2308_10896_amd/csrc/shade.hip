@@ -190,6 +190,8 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
     float shade = 0.f;
     for (int q = 0; q < R.light_count; ++q) {
         const ViewConst &l = views[render_lights[R.light_begin + q]];
+        // a cube face lights only the directions it owns: skip the fetch elsewhere
+        if (l.kind == kCubeFace && cube_face_of(x - l.pos[0], y - l.pos[1], z - l.pos[2]) != l.cube_face) continue;
         const float *M = l.M;
         const float cx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
         const float cy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];

@@ -93,6 +93,7 @@ class _BatchDesc:
             d.sigma = l.sigma
             d.min_variance = l.min_variance
             d.antialias = int(l.antialias)
+            d.cube_face = int(getattr(l, 'face', 0))
         cams = (L.CameraDesc * max(1, len(batch.cameras)))()
         for i, c in enumerate(batch.cameras):
             d = cams[i]

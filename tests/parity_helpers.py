@@ -126,3 +126,24 @@ def cone_ambiguous(batch, oracle_res, render, margin=1e-5):
         if f['cone_margin'] is not None:
             amb[view['flat']] |= f['cone_margin'] < margin
     return amb.reshape(cam.height, cam.width)
+
+
+def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4):
+    """Camera pixels whose discrete lookup decisions sit clear of their
+    thresholds in every light: the bilinear cell (floor of the map position,
+    where the fetch's derivative jumps) at least `cell_eps` texels from a
+    texel-centre line, and the spot-cone / cube-face choice at least
+    `face_eps` from its tie.  The kernels take these decisions in float32,
+    the oracle in float64, so a gradient test that weights only these pixels
+    compares one piecewise-smooth branch on both sides."""
+    r = batch.renders[render]
+    cam = batch.cameras[r.camera]
+    ok = np.ones(cam.height * cam.width, bool)
+    view = oracle_res['raw']['views'][render]
+    for li, f in oracle_res['flags'][render].items():
+        fr = f['frac']
+        near = (np.minimum(fr, 1.0 - fr) < cell_eps).any(0) & f['inside']
+        ok[view['flat']] &= ~near
+        if f['cone_margin'] is not None:
+            ok[view['flat']] &= f['cone_margin'] >= face_eps
+    return ok.reshape(cam.height, cam.width)

@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads and
 exports every function include/dsm.h declares, and argument validation
 rejects bad input before anything reaches the device."""
+import ctypes as C
 import os
 import re
 
@@ -75,3 +76,39 @@ def test_autotune_validation_on_host():
     if not torch.cuda.is_available():
         assert lib.dsm_autotune(C.byref(bd.desc), None, None, None, None, 1, None, None, C.byref(t), C.byref(s),
                                 C.byref(ms)) == 5
+
+
+def test_light_desc_mirror_matches_header():
+    """The binding's ctypes mirror of dsm_light_desc lists the header's
+    members in order (all 32-bit), so the two agree on size and offsets."""
+    from paper_2308_10896_amd import _lib
+    text = open(os.path.join(ROOT, 'include', 'dsm.h')).read()
+    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+    body = text[:text.index('} dsm_light_desc;')]
+    body = body[body.rindex('typedef struct {') + len('typedef struct {'):]
+    names = []
+    for decl in body.split(';'):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(None, 1)[1].split(','):
+            m = re.match(r'\s*([a-z_0-9]+)\s*(\[(\d+)\])?', part)
+            names.append((m.group(1), int(m.group(3) or 1)))
+    fields = [(n, C.sizeof(t) // 4) for n, t in _lib.LightDesc._fields_]
+    assert fields == names
+    assert C.sizeof(_lib.LightDesc) == 4 * sum(k for _, k in names)
+
+
+def test_cube_face_light_validation_on_host():
+    """A cube-face light needs a face index in 0..5; unknown light types are
+    rejected; both before any device call."""
+    import scenegen as sg
+    from paper_2308_10896_amd import _lib
+    lib = _lib.lib()
+    for face, typ in ((6, 3), (-1, 3), (0, 4)):
+        b = sg.cube_light_scene(resolution=32, view=32)
+        bd = dsm._BatchDesc(b)
+        bd.desc.lights[2].cube_face = face
+        bd.desc.lights[2].type = typ
+        h = C.c_void_p()
+        assert lib.dsm_plan_create(C.byref(bd.desc), 0, 0, C.byref(h)) == 1
