@@ -295,14 +295,17 @@ def other_configs(stream, steps=10, warmup=3):
     """Forward + backward renders/s of the other workloads (one captured
     graph per step, inputs resident, default tile side 8): the tiny cube
     scene, the icosphere under a spot light, the 128-render multi-view
-    sphere and the 330k-triangle complex scene."""
+    sphere, the 330k-triangle complex scene and an omnidirectional point
+    light (six 512^2 cube faces) over a ground with four occluders."""
     import torch
     import scenegen as sg
     from paper_2308_10896_amd import dsm
     res = {}
     for name, make in (('tiny cube, 256^2', sg.config0), ('icosphere, spot, 512^2', sg.config1),
                        ('multi-view sphere, 8 lights x 16 cameras, 1024^2 maps', sg.config3),
-                       ('complex scene, 330k triangles, 3 lights at 2048^2, 1920x1080', sg.config4)):
+                       ('complex scene, 330k triangles, 3 lights at 2048^2, 1920x1080', sg.config4),
+                       ('omnidirectional light, 6 cube faces at 512^2, 512^2 view',
+                        lambda: sg.cube_light_scene(resolution=512, view=512))):
         batch = make()
         dev = torch.device('cuda:0')
         plan = dsm.Plan(batch)

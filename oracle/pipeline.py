@@ -299,6 +299,8 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
                                                 torch.floor(sy).detach().numpy()]),
                                 frac=np.stack([(sx - torch.floor(sx)).detach().numpy(),
                                                (sy - torch.floor(sy)).detach().numpy()]),
+                                var_ratio=((m[:, 1] - m[:, 0] ** 2) / L.min_variance).detach().numpy()
+                                if L.min_variance > 0 else None,
                                 cone_margin=None if margin is None else margin.numpy())
         img0 = torch.zeros(W * H, batch.channels, dtype=D)
         img0 = img0.index_put((torch.as_tensor(flat),), col)

@@ -128,14 +128,17 @@ def cone_ambiguous(batch, oracle_res, render, margin=1e-5):
     return amb.reshape(cam.height, cam.width)
 
 
-def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4):
+def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4, var_eps=0.05):
     """Camera pixels whose discrete lookup decisions sit clear of their
     thresholds in every light: the bilinear cell (floor of the map position,
     where the fetch's derivative jumps) at least `cell_eps` texels from a
-    texel-centre line, and the spot-cone / cube-face choice at least
-    `face_eps` from its tie.  The kernels take these decisions in float32,
-    the oracle in float64, so a gradient test that weights only these pixels
-    compares one piecewise-smooth branch on both sides."""
+    texel-centre line, the spot-cone / cube-face choice at least `face_eps`
+    from its tie, and, in the shadowed branch, m2 - m1^2 at least a fraction
+    `var_eps` away from the variance floor (the floor switches the
+    derivative through sigma^2 on and off, and float32 forms m2 - m1^2 with
+    an absolute error of a few 1e-7).  The kernels take these decisions in
+    float32, the oracle in float64, so a gradient test that weights only
+    these pixels compares one piecewise-smooth branch on both sides."""
     r = batch.renders[render]
     cam = batch.cameras[r.camera]
     ok = np.ones(cam.height * cam.width, bool)
@@ -144,6 +147,9 @@ def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4):
         fr = f['frac']
         near = (np.minimum(fr, 1.0 - fr) < cell_eps).any(0) & f['inside']
         ok[view['flat']] &= ~near
+        if f['var_ratio'] is not None:
+            shadowed = f['inside'] & ~f['branch']
+            ok[view['flat']] &= ~(shadowed & (np.abs(f['var_ratio'] - 1.0) < var_eps))
         if f['cone_margin'] is not None:
             ok[view['flat']] &= f['cone_margin'] >= face_eps
     return ok.reshape(cam.height, cam.width)
