@@ -7,7 +7,10 @@ Per light (Alg. 1, RenderShadowMap):
     light (Sec. 3: Euclidean for point/spot lights, from a plane outside the
     scene for directional lights), normalized z = d / far;
     f = z, f^2 = z * z formed before smoothing (Sec. 5); background texels
-    hold the far value (1, 1);
+    hold the far value (1, 1).  Exponential maps (a pre-warp g = exp of the
+    depth before filtering, one of the alternatives Sec. 3 lists; light
+    bleeding, supplementary limitations) store f = exp(c z), f^2 = exp(2 c z)
+    instead, background (exp(c), exp(2c));
   * smoothing at primitive borders gives (f~, f^2~) (Sec. 4);
   * m1 = G f~, m2 = G f^2~ with G a separable box or Gaussian filter of odd
     size k, clamp-to-edge (Eq. moment1, moment2; Sec. 5 "Filter").
@@ -16,6 +19,9 @@ details; Alg. 2, ComputeVisibility):
   * u = L(x); bilinear fetch of (m1, m2) at u (clamp-to-edge);
   * mu = m1, sigma^2 = max(m2 - m1^2, eps); v = 1 if d <= mu, else
     sigma^2 / (sigma^2 + (d - mu)^2) (Sec. 3, one-sided Chebyshev bound);
+    exponential maps compare the warped depth exp(c z) and scale the floor
+    by the warp's slope, eps (c exp(c z))^2; a light-bleeding reduction
+    amount a > 0 then maps v to clamp((v - a) / (1 - a), 0, 1);
   * colour = sum over lights of albedo * max(0, n . omega) * v * I * cone;
     cone is the hard mask of a spot light's cone, or of the directions a
     cube face owns (1 for directional and point lights);
@@ -125,6 +131,32 @@ def chebyshev(m1, m2, d, eps):
     return torch.where(d <= mu, torch.ones_like(v), v)
 
 
+def warp_depth(z, c):
+    """The stored depth function: exp(c z) for exponential maps (c > 0), the
+    plain normalized depth otherwise."""
+    return torch.exp(c * z) if c > 0 else z
+
+
+def lookup_visibility(m1, m2, z, L):
+    """Visibility of a receiver at normalized depth z from filtered moments
+    (Sec. 3): the Chebyshev bound on the (warped) depth, then the
+    light-bleeding reduction.  Returns (v, warped depth, variance floor)."""
+    c = L.warp_exponent
+    if c > 0:
+        w = torch.exp(c * z)
+        eps = L.min_variance * (c * w) ** 2
+        var = torch.maximum(m2 - m1 * m1, eps)
+        diff = w - m1
+        v = torch.where(w <= m1, torch.ones_like(var), var / (var + diff * diff))
+    else:
+        w, eps = z, L.min_variance
+        v = chebyshev(m1, m2, z, L.min_variance)
+    a = L.bleed_reduction
+    if a > 0:
+        v = torch.clamp((v - a) / (1.0 - a), 0.0, 1.0)
+    return v, w, eps
+
+
 def smooth_edges(img, pairs, clip, W, H):
     """Apply the silhouette antialiasing blend for the fixed pairs.
 
@@ -193,6 +225,14 @@ def light_distance(frame, x):
     return d / frame['far']
 
 
+def _no_bleed(L):
+    class _V:
+        warp_exponent = L.warp_exponent
+        min_variance = L.min_variance
+        bleed_reduction = 0.0
+    return _V
+
+
 @dataclass
 class Options:
     camera_antialias: bool = True
@@ -225,10 +265,11 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
         fv = faces[t]
         b = perspective_barycentrics(clip[fv[:, 0]], clip[fv[:, 1]], clip[fv[:, 2]], px, py)
         x = (b[:, :, None] * verts[fv]).sum(1)
-        z = light_distance(fr, x)
-        F0 = torch.ones(S * S, 2, dtype=D)
+        f = warp_depth(light_distance(fr, x), L.warp_exponent)
+        far = warp_depth(torch.ones((), dtype=D), L.warp_exponent)
+        F0 = torch.stack([far, far * far]).expand(S * S, 2).clone()
         fl = torch.as_tensor(flat)
-        F0 = F0.index_put((fl,), torch.stack([z, z * z], 1))
+        F0 = F0.index_put((fl,), torch.stack([f, f * f], 1))
         F1 = smooth_edges(F0, rv['pairs'], clip, S, S) if L.antialias else F0
         taps = filter_taps(L.filter, L.k, L.sigma)
         Mm = filter_separable(F1.T.reshape(2, S, S), taps)
@@ -270,7 +311,8 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
             sy = torch.where(inside, sy, torch.zeros_like(sy))
             m = bilinear(ls['M'], sx, sy)
             z = light_distance(fr, x)
-            vis = chebyshev(m[:, 0], m[:, 1], z, L.min_variance)
+            vis_raw = lookup_visibility(m[:, 0], m[:, 1], z, _no_bleed(L))[0]
+            vis, zw, eps = lookup_visibility(m[:, 0], m[:, 1], z, L)
             vis = torch.where(inside, vis, torch.ones_like(vis))
             if fr['kind'] == 'directional':
                 omega = (-fr['w']).expand_as(x)
@@ -293,14 +335,16 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
                 margin = torch.as_tensor((ad[:, 2] - ad[:, 1]) / np.maximum(ad[:, 2], 1e-30))
             col = col + rho * (lam * vis * L.intensity * cone)[:, None]
             fl_flags[li] = dict(inside=inside.numpy(), lit_side=(ndl > 0).detach().numpy(),
-                                branch=(z <= m[:, 0]).detach().numpy(),
-                                clamp=(m[:, 1] - m[:, 0] ** 2 < L.min_variance).detach().numpy(),
+                                branch=(zw <= m[:, 0]).detach().numpy(),
+                                clamp=(m[:, 1] - m[:, 0] ** 2 < eps).detach().numpy(),
                                 floor=np.stack([torch.floor(sx).detach().numpy(),
                                                 torch.floor(sy).detach().numpy()]),
                                 frac=np.stack([(sx - torch.floor(sx)).detach().numpy(),
                                                (sy - torch.floor(sy)).detach().numpy()]),
-                                var_ratio=((m[:, 1] - m[:, 0] ** 2) / L.min_variance).detach().numpy()
+                                var_ratio=((m[:, 1] - m[:, 0] ** 2) / eps).detach().numpy()
                                 if L.min_variance > 0 else None,
+                                bleed_margin=(vis_raw - L.bleed_reduction).abs().detach().numpy()
+                                if L.bleed_reduction > 0 else None,
                                 cone_margin=None if margin is None else margin.numpy())
         img0 = torch.zeros(W * H, batch.channels, dtype=D)
         img0 = img0.index_put((torch.as_tensor(flat),), col)

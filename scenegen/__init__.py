@@ -66,6 +66,8 @@ class Light:
     min_variance: float = MIN_VARIANCE
     antialias: bool = True
     face: int = 0                # 'cubeface': face index 0..5 (+x, -x, +y, -y, +z, -z)
+    warp_exponent: float = 0.0   # > 0: exponential maps storing exp(c z), exp(2 c z)
+    bleed_reduction: float = 0.0  # light-bleeding reduction amount in [0, 1)
 
 
 @dataclass
