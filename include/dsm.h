@@ -92,6 +92,17 @@ typedef struct dsm_plan dsm_plan;
  * Depths are stored as z = d / zfar.  `k` is the odd filter size of the
  * moment filter (box or Gaussian with std. dev. sigma in texels; sigma <= 0
  * means (k-1)/3).  min_variance floors sigma^2 = m2 - m1^2.
+ *
+ * Alternative pre-filtered maps (Sec. 3 lists pre-warps g(f) such as exp;
+ * light bleeding, supplementary limitations):
+ *   warp_exponent c > 0 stores exp(c z) and exp(2 c z) instead of z and z^2
+ *   (background exp(c), exp(2c)); the lookup compares exp(c d / zfar) with
+ *   the filtered first moment and floors sigma^2 at
+ *   min_variance * (c exp(c d / zfar))^2.  0 <= c <= 40 (larger values
+ *   overflow float32 in the floor); 0 keeps plain variance maps.
+ *   bleed_reduction a in [0, 1) maps the visibility v to
+ *   clamp((v - a) / (1 - a), 0, 1), cutting light bleeding where occluders
+ *   at several depths share a filter window; 0 leaves v unchanged.
  */
 typedef struct {
     int32_t type;          /* DSM_LIGHT_*                                   */
@@ -110,6 +121,8 @@ typedef struct {
     float min_variance;
     int32_t antialias;     /* smooth the light view at primitive borders    */
     int32_t cube_face;     /* DSM_LIGHT_CUBE_FACE: face 0..5; else ignored  */
+    float warp_exponent;   /* exponential maps: c in [0, 40]; 0 = plain     */
+    float bleed_reduction; /* light-bleeding reduction amount in [0, 1)     */
 } dsm_light_desc;
 
 /* A perspective viewer camera (fixed; no gradient). */

@@ -30,7 +30,8 @@ class LightDesc(C.Structure):
                 ('fov_deg', C.c_float), ('dir_distance', C.c_float), ('ortho_half', C.c_float),
                 ('znear', C.c_float), ('zfar', C.c_float), ('intensity', C.c_float),
                 ('resolution', C.c_int32), ('filter', C.c_int32), ('k', C.c_int32), ('sigma', C.c_float),
-                ('min_variance', C.c_float), ('antialias', C.c_int32), ('cube_face', C.c_int32)]
+                ('min_variance', C.c_float), ('antialias', C.c_int32), ('cube_face', C.c_int32),
+                ('warp_exponent', C.c_float), ('bleed_reduction', C.c_float)]
 
 
 class CameraDesc(C.Structure):

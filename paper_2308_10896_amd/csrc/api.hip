@@ -101,6 +101,9 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         const dsm_light_desc &x = d->lights[l];
         if (x.type < 0 || x.type > DSM_LIGHT_CUBE_FACE || x.scene < 0 || x.scene >= B) return DSM_ERR_INVALID_ARG;
         if (x.type == DSM_LIGHT_CUBE_FACE && (x.cube_face < 0 || x.cube_face > 5)) return DSM_ERR_INVALID_ARG;
+        if (!(x.warp_exponent >= 0.f && x.warp_exponent <= 40.f) ||
+            !(x.bleed_reduction >= 0.f && x.bleed_reduction < 1.f))
+            return DSM_ERR_INVALID_ARG;
         if (!valid_filter(x.resolution, x.filter, x.k)) return DSM_ERR_INVALID_ARG;
         if (!(x.znear > 0 && x.zfar > x.znear) || !std::isfinite(x.zfar)) return DSM_ERR_INVALID_ARG;
         if (x.type == DSM_LIGHT_DIRECTIONAL && !(x.ortho_half > 0 && x.dir_distance > 0)) return DSM_ERR_INVALID_ARG;
@@ -185,6 +188,8 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
                  : x.type == DSM_LIGHT_SPOT    ? kSpot
                                                : kCubeFace;
         v.cube_face = v.kind == kCubeFace ? x.cube_face : 0;
+        v.warp_c = x.warp_exponent;
+        v.bleed = x.bleed_reduction;
         v.zfar = x.zfar;
         v.cos_half = (float)cos((double)x.fov_deg * (M_PI / 180.0) / 2.0);
         v.intensity = x.intensity;

@@ -41,7 +41,28 @@ struct ViewConst {
     int part_off;       // light views: first per-tile slot of the backward light-frame partials
     int part_gm_off;    // light views: first per-vertex-block slot of the dL/dM partials
     int cube_face;      // cube-face lights: face 0..5 (+x, -x, +y, -y, +z, -z)
+    float warp_c;       // light views: exponential maps store exp(c z), exp(2 c z); 0 = plain z, z^2
+    float bleed;        // light views: light-bleeding reduction amount
 };
+
+// Receiver depth as the lookup compares it, and the variance floor:
+// exponential maps compare exp(c z) and floor sigma^2 at min_var (c exp(c z))^2
+// (the floor follows the warp's slope); plain maps use z and min_var.
+__device__ __forceinline__ void warp_receiver(const ViewConst &l, float zz, float &zw, float &floor_v) {
+    if (l.warp_c > 0.f) {
+        zw = expf(l.warp_c * zz);
+        const float s = l.warp_c * zw;
+        floor_v = l.min_var * (s * s);
+    } else {
+        zw = zz;
+        floor_v = l.min_var;
+    }
+}
+
+// Light-bleeding reduction: v -> clamp((v - a) / (1 - a), 0, 1) for a > 0.
+__device__ __forceinline__ float bleed_reduce(const ViewConst &l, float v) {
+    return l.bleed > 0.f ? fminf(fmaxf((v - l.bleed) / (1.f - l.bleed), 0.f), 1.f) : v;
+}
 
 // Cube face owning the direction d from an omnidirectional light: the axis of
 // the largest |d_a| (the first one on ties) and its sign, face 2a (+) or

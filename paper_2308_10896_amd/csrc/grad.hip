@@ -398,7 +398,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         const float cw = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
         const float ux = cx / cw, uy = cy / cw;
         const bool inside = cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f;
-        float vis = 1.f, zz = 0.f, m1 = 0.f, m2 = 0.f, var = 0.f, dd = 0.f, fx = 0.f, fy = 0.f;
+        float vis = 1.f, visr = 1.f, zz = 0.f, zw = 0.f, floor_v = 0.f, m1 = 0.f, m2 = 0.f, var = 0.f, dd = 0.f,
+              fx = 0.f, fy = 0.f;
         long long o00 = 0, o01 = 0, o10 = 0, o11 = 0;
         int ixs = 0, iys = 0;
         hits[q].gm1 = 0.f;
@@ -431,9 +432,11 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                 depth = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
             }
             zz = depth / l.zfar;
-            var = fmaxf(m2 - m1 * m1, l.min_var);
-            dd = zz - m1;
-            vis = (zz <= m1) ? 1.f : var / (var + dd * dd);
+            warp_receiver(l, zz, zw, floor_v);
+            var = fmaxf(m2 - m1 * m1, floor_v);
+            dd = zw - m1;
+            visr = (zw <= m1) ? 1.f : var / (var + dd * dd);
+            vis = bleed_reduce(l, visr);
         }
         float ox, oy, oz, olen = 1.f;
         if (l.kind == kDirectional) {
@@ -468,14 +471,32 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             gpos[0] += gpx; gpos[1] += gpy; gpos[2] += gpz;
             gx[0] -= gpx; gx[1] -= gpy; gx[2] -= gpz;
         }
-        if (inside && gvis != 0.f && zz > m1) {
+        // through the bleeding reduction: slope 1 / (1 - a) on [a, 1], else 0
+        const float gvr = l.bleed > 0.f ? (visr >= l.bleed ? gvis / (1.f - l.bleed) : 0.f) : gvis;
+        if (inside && gvr != 0.f && zw > m1) {
             const float qd = var + dd * dd;
-            const float dv_dmu = 2.f * var * dd / (qd * qd);
-            const bool clamped = m2 - m1 * m1 < l.min_var;
-            const float dv_dvar = clamped ? 0.f : dd * dd / (qd * qd);
-            const float gm1 = gvis * (dv_dmu - 2.f * m1 * dv_dvar);
-            const float gm2 = gvis * dv_dvar;
-            const float gdepth = -gvis * dv_dmu / l.zfar;
+            float dv_dmu, dv_dvar_raw;
+            if (l.warp_c > 0.f) {
+                // exponential maps: the squares of var and dd overflow float32
+                const float tv = var / qd, td = dd / qd;
+                dv_dmu = 2.f * tv * td;
+                dv_dvar_raw = td * td;
+            } else {
+                dv_dmu = 2.f * var * dd / (qd * qd);
+                dv_dvar_raw = dd * dd / (qd * qd);
+            }
+            const bool clamped = m2 - m1 * m1 < floor_v;
+            const float dv_dvar = clamped ? 0.f : dv_dvar_raw;
+            const float gm1 = gvr * (dv_dmu - 2.f * m1 * dv_dvar);
+            const float gm2 = gvr * dv_dvar;
+            // d v / d (receiver depth): through d - mu, through the floor when
+            // it binds and follows the warp, and through the warp itself
+            float dv_dzw = -dv_dmu;
+            if (l.warp_c > 0.f) {
+                if (clamped) dv_dzw += dv_dvar_raw * (2.f * l.min_var * l.warp_c * l.warp_c * zw);
+                dv_dzw *= l.warp_c * zw;
+            }
+            const float gdepth = gvr * dv_dzw / l.zfar;
             if (l.kind == kDirectional) {
                 gx[0] += gdepth * l.dir[0]; gx[1] += gdepth * l.dir[1]; gx[2] += gdepth * l.dir[2];
                 gpos[0] -= gdepth * l.dir[0]; gpos[1] -= gdepth * l.dir[1]; gpos[2] -= gdepth * l.dir[2];
@@ -804,7 +825,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
             const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
             const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
             const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
-            const float gz = g0 + 2.f * f0a[pp] * g1;
+            // F0 = (f, f^2), f = z, or exp(c z) for exponential maps
+            const float gz = l.warp_c > 0.f ? l.warp_c * f0a[pp] * (g0 + 2.f * f0a[pp] * g1) : g0 + 2.f * f0a[pp] * g1;
             const float gdepth = gz / l.zfar;
             float gx[3];
             if (l.kind == kDirectional) {

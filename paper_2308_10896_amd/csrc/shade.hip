@@ -74,8 +74,9 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVer
         const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
         const float zz = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
         z = light_depth(l, x, y, zz);
-        z2 = z * z;
     }
+    if (l.warp_c > 0.f) z = expf(l.warp_c * z);     // exponential maps
+    z2 = z * z;
     F0[l.map_off + t] = z;
     F0[l.map_off + (long long)S * S + t] = z2;
 }
@@ -203,10 +204,11 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
             const float sx = (ux + 1.f) * (0.5f * S) - 0.5f;
             const float sy = (1.f - uy) * (0.5f * S) - 0.5f;
             const Fetch m = bilinear2(maps, l.map_off, S, sx, sy);
-            const float zz = light_depth(l, x, y, z);
-            const float var = fmaxf(m.m2 - m.m1 * m.m1, l.min_var);
-            const float dd = zz - m.m1;
-            vis = (zz <= m.m1) ? 1.f : var / (var + dd * dd);
+            float zw, floor_v;
+            warp_receiver(l, light_depth(l, x, y, z), zw, floor_v);
+            const float var = fmaxf(m.m2 - m.m1 * m.m1, floor_v);
+            const float dd = zw - m.m1;
+            vis = bleed_reduce(l, (zw <= m.m1) ? 1.f : var / (var + dd * dd));
         }
         float ox, oy, oz;
         if (l.kind == kDirectional) {

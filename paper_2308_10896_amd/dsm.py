@@ -94,6 +94,8 @@ class _BatchDesc:
             d.min_variance = l.min_variance
             d.antialias = int(l.antialias)
             d.cube_face = int(getattr(l, 'face', 0))
+            d.warp_exponent = float(getattr(l, 'warp_exponent', 0.0))
+            d.bleed_reduction = float(getattr(l, 'bleed_reduction', 0.0))
         cams = (L.CameraDesc * max(1, len(batch.cameras)))()
         for i, c in enumerate(batch.cameras):
             d = cams[i]

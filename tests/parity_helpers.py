@@ -128,7 +128,7 @@ def cone_ambiguous(batch, oracle_res, render, margin=1e-5):
     return amb.reshape(cam.height, cam.width)
 
 
-def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4, var_eps=0.05):
+def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4, var_eps=0.05, bleed_eps=1e-3):
     """Camera pixels whose discrete lookup decisions sit clear of their
     thresholds in every light: the bilinear cell (floor of the map position,
     where the fetch's derivative jumps) at least `cell_eps` texels from a
@@ -136,7 +136,8 @@ def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4, var
     from its tie, and, in the shadowed branch, m2 - m1^2 at least a fraction
     `var_eps` away from the variance floor (the floor switches the
     derivative through sigma^2 on and off, and float32 forms m2 - m1^2 with
-    an absolute error of a few 1e-7).  The kernels take these decisions in
+    an absolute error of a few 1e-7), and the visibility at least `bleed_eps`
+    from the light-bleeding reduction's threshold.  The kernels take these decisions in
     float32, the oracle in float64, so a gradient test that weights only
     these pixels compares one piecewise-smooth branch on both sides."""
     r = batch.renders[render]
@@ -150,6 +151,8 @@ def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4, var
         if f['var_ratio'] is not None:
             shadowed = f['inside'] & ~f['branch']
             ok[view['flat']] &= ~(shadowed & (np.abs(f['var_ratio'] - 1.0) < var_eps))
+        if f.get('bleed_margin') is not None:
+            ok[view['flat']] &= ~(f['inside'] & (f['bleed_margin'] < bleed_eps))
         if f['cone_margin'] is not None:
             ok[view['flat']] &= f['cone_margin'] >= face_eps
     return ok.reshape(cam.height, cam.width)
