@@ -24,6 +24,7 @@ values while autograd differentiates the float64 construction
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -110,6 +111,83 @@ def cube_face_of(d):
     a = np.argmax(np.abs(d), axis=1)
     neg = d[np.arange(len(d)), a] < 0
     return 2 * a + neg.astype(np.int64)
+
+
+def cube_face_basis(f):
+    """Viewing axis, right and up vectors of cube face f (look_at's frame):
+    a texel at NDC (u, v) of the face's map looks along a + u s + v up."""
+    a = np.array(CUBE_AXES[f])
+    s = np.cross(a, np.array(CUBE_UPS[f]))
+    s = s / np.linalg.norm(s)
+    return a, s, np.cross(s, a)
+
+
+# edges of a face's map: 0 left (u = -1), 1 right (u = +1), 2 top (v = +1), 3 bottom (v = -1)
+def cube_edge_table():
+    """table[f][e] = (g, e', flip): the face across edge e of face f, the edge
+    of g's map on the same cube edge, and whether texel indices along the
+    edge run backwards from one map to the other.  Derived from the faces'
+    frames: the two points of f's edge at along-coordinates -1/2 and +1/2 are
+    projected into g."""
+    table = []
+    for f in range(6):
+        a, s, u = cube_face_basis(f)
+        row = []
+        for e in range(4):
+            out = (-s, s, u, -u)[e]
+            g = [k for k in range(6) if np.allclose(CUBE_AXES[k], out)][0]
+            ag, sg, ug = cube_face_basis(g)
+            along = u if e < 2 else s
+            pts = [a + out + tau * along for tau in (-0.5, 0.5)]
+            uv = [(p @ sg / (p @ ag), p @ ug / (p @ ag)) for p in pts]
+            if abs(abs(uv[0][0]) - 1) < 1e-9 and abs(uv[0][0] - uv[1][0]) < 1e-9:
+                e2 = 0 if uv[0][0] < 0 else 1
+                g_along = [q[1] for q in uv]
+            else:
+                e2 = 2 if uv[0][1] > 0 else 3
+                g_along = [q[0] for q in uv]
+            # texel index direction as tau grows: v runs against j, u with i
+            df = -1 if e < 2 else 1
+            dg = np.sign(g_along[1] - g_along[0]) * (-1 if e2 < 2 else 1)
+            row.append((g, e2, bool(df != dg)))
+        table.append(row)
+    return table
+
+
+@functools.lru_cache(maxsize=16)
+def cube_pad_sources(S, P):
+    """For each face f, the (6 S S)-flat index of the texel every position of
+    its map padded by P texels copies: itself inside; across an edge, the
+    neighbouring face's texel at depth k - 1 from the shared edge for the
+    k-th padded texel, at the matching position along the edge; in a corner
+    block, the face's own corner texel.  Returns (6, S + 2P, S + 2P)."""
+    tab = cube_edge_table()
+    Sp = S + 2 * P
+    out = np.zeros((6, Sp, Sp), np.int64)
+    for f in range(6):
+        for pj in range(Sp):
+            for pi in range(Sp):
+                i, j = pi - P, pj - P
+                ins_i, ins_j = 0 <= i < S, 0 <= j < S
+                if ins_i and ins_j:
+                    g, jj, ii = f, j, i
+                elif not ins_i and not ins_j:
+                    g, jj, ii = f, min(max(j, 0), S - 1), min(max(i, 0), S - 1)
+                else:
+                    if i < 0:
+                        e, k, t = 0, -i, j
+                    elif i >= S:
+                        e, k, t = 1, i - S + 1, j
+                    elif j < 0:
+                        e, k, t = 2, -j, i
+                    else:
+                        e, k, t = 3, j - S + 1, i
+                    g, e2, flip = tab[f][e]
+                    t2 = S - 1 - t if flip else t
+                    dpt = k - 1
+                    jj, ii = ((t2, dpt), (t2, S - 1 - dpt), (dpt, t2), (S - 1 - dpt, t2))[e2]
+                out[f, pj, pi] = (g * S + jj) * S + ii
+    return out
 
 
 def light_frame(light, param):

@@ -271,10 +271,27 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
         fl = torch.as_tensor(flat)
         F0 = F0.index_put((fl,), torch.stack([f, f * f], 1))
         F1 = smooth_edges(F0, rv['pairs'], clip, S, S) if L.antialias else F0
-        taps = filter_taps(L.filter, L.k, L.sigma)
-        Mm = filter_separable(F1.T.reshape(2, S, S), taps)
         lights.append(dict(frame=fr, rv=rv, F0=F0.T.reshape(2, S, S), F1=F1.T.reshape(2, S, S),
-                           M=Mm, taps=taps))
+                           taps=filter_taps(L.filter, L.k, L.sigma), pad=0))
+    for li, L in enumerate(batch.lights):
+        ls = lights[li]
+        if L.kind == 'cubeface':
+            # the six faces of one cube are consecutive lights; each face's
+            # map is padded from its neighbours across the cube's edges before
+            # filtering, so filter and fetch continue across the seams
+            base = li - L.face
+            group = batch.lights[base:base + 6]
+            assert [q.face for q in group] == list(range(6)) and all(q.kind == 'cubeface' for q in group)
+            assert all((q.resolution, q.k, q.filter, q.sigma) == (L.resolution, L.k, L.filter, L.sigma) for q in group)
+            S = L.resolution
+            P = (L.k - 1) // 2 + 1
+            src = cameras.cube_pad_sources(S, P)[L.face]
+            stack = torch.stack([lights[base + g]['F1'] for g in range(6)], 1).reshape(2, 6 * S * S)
+            Fp = stack[:, torch.as_tensor(src.ravel())].reshape(2, S + 2 * P, S + 2 * P)
+            Mp = filter_separable(Fp, ls['taps'])
+            ls.update(pad=P, Mpad=Mp, M=Mp[:, P:P + S, P:P + S])
+        else:
+            ls['M'] = filter_separable(ls['F1'], ls['taps'])
     images, views, flags = [], [], []
     for R in batch.renders:
         cam = batch.cameras[R.camera]
@@ -309,7 +326,8 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
             sy = (1.0 - cl[:, 1] / cl[:, 3]) * (S / 2.0) - 0.5
             sx = torch.where(inside, sx, torch.zeros_like(sx))
             sy = torch.where(inside, sy, torch.zeros_like(sy))
-            m = bilinear(ls['M'], sx, sy)
+            P = ls['pad']
+            m = bilinear(ls['Mpad'], sx + P, sy + P) if P else bilinear(ls['M'], sx, sy)
             z = light_distance(fr, x)
             vis_raw = lookup_visibility(m[:, 0], m[:, 1], z, _no_bleed(L))[0]
             vis, zw, eps = lookup_visibility(m[:, 0], m[:, 1], z, L)

@@ -157,3 +157,49 @@ def test_cube_light_hard_shadow_limit_equals_ray_casting():
     # shadowed samples in the -y, +x and -z faces and on both sides of the -x / +z seam
     faces_in_shadow = set(owner[idx][shadow_ray].tolist())
     assert {0, 1, 3, 4, 5} <= faces_in_shadow, faces_in_shadow
+
+
+def test_cube_edge_table_is_symmetric_and_covers_every_edge():
+    """Each cube edge is shared by exactly two face-map edges, each pointing at
+    the other with the same index direction; 24 map edges, 12 cube edges."""
+    tab = cameras.cube_edge_table()
+    seen = set()
+    for f in range(6):
+        for e in range(4):
+            g, e2, flip = tab[f][e]
+            assert g != f and tab[g][e2] == (f, e, flip)
+            seen.add(frozenset([(f, e), (g, e2)]))
+    assert len(seen) == 12
+
+
+@pytest.mark.parametrize('S,P', [(16, 2), (33, 4)])
+def test_cube_padding_follows_the_directions(S, P):
+    """Pad maps filled with a smooth function of direction: every copied
+    texel lies within a few texels (in angle) of the direction its padded
+    position looks along when face f's plane is continued across the edge;
+    a wrong neighbour, edge or index direction misses by about a face."""
+    c = np.array([0.3, -0.8, 0.5])
+
+    def phi(d):
+        return (d / np.linalg.norm(d, axis=-1, keepdims=True)) @ c
+
+    vals = np.zeros((6, S, S))
+    ndc = (2 * np.arange(S) + 1) / S - 1
+    for f in range(6):
+        a, s, u = cameras.cube_face_basis(f)
+        U, V = np.meshgrid(ndc, -ndc)
+        vals[f] = phi(a + U[..., None] * s + V[..., None] * u)
+    src = cameras.cube_pad_sources(S, P)
+    Sp = S + 2 * P
+    pndc = (2 * (np.arange(Sp) - P) + 1) / S - 1
+    worst = 0.0
+    for f in range(6):
+        a, s, u = cameras.cube_face_basis(f)
+        U, V = np.meshgrid(pndc, -pndc)
+        out = (np.abs(U) > 1) ^ (np.abs(V) > 1)          # edge blocks, not corners
+        want = phi(a + U[..., None] * s + V[..., None] * u)
+        got = vals.ravel()[src[f]]
+        assert np.array_equal(got[P:P + S, P:P + S], vals[f])
+        worst = max(worst, np.abs(got - want)[out].max())
+    # |grad phi| <= |c| ~ 1 per radian; P texels of 2/S NDC each
+    assert worst < 2.5 * (2 * P / S), worst
