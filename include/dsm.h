@@ -87,8 +87,14 @@ typedef struct dsm_plan dsm_plan;
  *                through it), so six faces with one position light every
  *                direction exactly once.  Each face is a light of its own
  *                with its own map and parameter slot; the gradient for the
- *                shared position is the sum of the six.  Seams are filtered
- *                and fetched per face with clamp-to-edge.
+ *                shared position is the sum of the six.  The six faces of
+ *                one cube light are consecutive lights with cube_face 0..5
+ *                in order and equal scene, resolution, filter, k and sigma
+ *                (else DSM_ERR_INVALID_ARG); their parameters should hold
+ *                the same position.  Each face's map is padded with
+ *                (k - 1) / 2 + 1 texels copied from its neighbours across
+ *                the cube's edges before filtering, so the filter and the
+ *                bilinear fetch continue across the seams.
  * Depths are stored as z = d / zfar.  `k` is the odd filter size of the
  * moment filter (box or Gaussian with std. dev. sigma in texels; sigma <= 0
  * means (k-1)/3).  min_variance floors sigma^2 = m2 - m1^2.

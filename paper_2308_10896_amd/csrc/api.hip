@@ -17,6 +17,61 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
+// Frame of cube face f as integer vectors: viewing axis a = (-1)^s e_k for
+// f = 2k + s, up +z for the y faces and +y otherwise, right = a x up and the
+// camera's up u = right x a (the light camera's look-at frame).
+void cube_frame(int f, int a[3], int r[3], int u[3]) {
+    const int k = f >> 1;
+    int up[3] = {0, 0, 0};
+    up[k == 1 ? 2 : 1] = 1;
+    for (int i = 0; i < 3; ++i) a[i] = i == k ? ((f & 1) ? -1 : 1) : 0;
+    r[0] = a[1] * up[2] - a[2] * up[1];
+    r[1] = a[2] * up[0] - a[0] * up[2];
+    r[2] = a[0] * up[1] - a[1] * up[0];
+    u[0] = r[1] * a[2] - r[2] * a[1];
+    u[1] = r[2] * a[0] - r[0] * a[2];
+    u[2] = r[0] * a[1] - r[1] * a[0];
+}
+
+int dot3i(const int x[3], const int y[3]) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; }
+
+// The face across edge e (0 left, 1 right, 2 top, 3 bottom of the map) of
+// cube face f, the edge of that face's map on the same cube edge, and whether
+// texel indices along the edge run in opposite directions: packed as
+// g | e' << 3 | reversed << 5.  Two points of the edge, at along-coordinates
+// -1/2 and +1/2 (scaled by 2 to stay integer), are expressed in g's frame.
+int cube_edge_neighbour(int f, int e) {
+    int a[3], r[3], u[3];
+    cube_frame(f, a, r, u);
+    int out[3], along[3];
+    for (int i = 0; i < 3; ++i) {
+        out[i] = e == 0 ? -r[i] : e == 1 ? r[i] : e == 2 ? u[i] : -u[i];
+        along[i] = e < 2 ? u[i] : r[i];
+    }
+    int g = 0;
+    for (int i = 0; i < 3; ++i)
+        if (out[i] != 0) g = 2 * i + (out[i] < 0 ? 1 : 0);
+    int ag[3], rg[3], ug[3];
+    cube_frame(g, ag, rg, ug);
+    int pm[3], pp[3];                     // 2 x the two edge points
+    for (int i = 0; i < 3; ++i) {
+        pm[i] = 2 * a[i] + 2 * out[i] - along[i];
+        pp[i] = 2 * a[i] + 2 * out[i] + along[i];
+    }
+    // in g's map (NDC x2): the edge coordinate is +-2 at both points
+    int e2, dg;
+    if (dot3i(pm, rg) == dot3i(pp, rg)) {
+        e2 = dot3i(pm, rg) < 0 ? 0 : 1;
+        dg = -(dot3i(pp, ug) - dot3i(pm, ug));        // index runs against v
+    } else {
+        e2 = dot3i(pm, ug) > 0 ? 2 : 3;
+        dg = dot3i(pp, rg) - dot3i(pm, rg);           // index runs with u
+    }
+    const int df = e < 2 ? -1 : 1;                    // f: along is v for left/right, u for top/bottom
+    const bool reversed = (df > 0) != (dg > 0);
+    return g | (e2 << 3) | ((reversed ? 1 : 0) << 5);
+}
+
 __global__ void zero_kernel(unsigned *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -100,7 +155,18 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     for (int l = 0; l < L; ++l) {
         const dsm_light_desc &x = d->lights[l];
         if (x.type < 0 || x.type > DSM_LIGHT_CUBE_FACE || x.scene < 0 || x.scene >= B) return DSM_ERR_INVALID_ARG;
-        if (x.type == DSM_LIGHT_CUBE_FACE && (x.cube_face < 0 || x.cube_face > 5)) return DSM_ERR_INVALID_ARG;
+        if (x.type == DSM_LIGHT_CUBE_FACE) {
+            // the six faces of one cube light are consecutive lights, faces 0..5
+            // in order, with one scene, map size and filter
+            if (x.cube_face < 0 || x.cube_face > 5 || l - x.cube_face < 0 || l - x.cube_face + 5 >= L)
+                return DSM_ERR_INVALID_ARG;
+            for (int g = 0; g < 6; ++g) {
+                const dsm_light_desc &y = d->lights[l - x.cube_face + g];
+                if (y.type != DSM_LIGHT_CUBE_FACE || y.cube_face != g || y.scene != x.scene ||
+                    y.resolution != x.resolution || y.k != x.k || y.filter != x.filter || y.sigma != x.sigma)
+                    return DSM_ERR_INVALID_ARG;
+            }
+        }
         if (!(x.warp_exponent >= 0.f && x.warp_exponent <= 40.f) ||
             !(x.bleed_reduction >= 0.f && x.bleed_reduction < 1.f))
             return DSM_ERR_INVALID_ARG;
@@ -156,6 +222,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
 
     // views: lights then cameras
     long long clip = 0, tri = 0, pix = 0, maps = 0, tiles = 0, part_light = 0, part_gm = 0, part_render = 0;
+    long long fmaps = 0, padmaps = 0;
     auto add_view = [&](ViewConst &v, int scene, int W, int H) {
         v.scene = scene;
         v.W = W;
@@ -198,6 +265,23 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         add_view(v, x.scene, x.resolution, x.resolution);
         v.map_off = maps;
         maps += 2LL * x.resolution * x.resolution;
+        // filtered maps of a cube face keep (k - 1) / 2 + 1 texels of its
+        // neighbours around it: enough for the filter to reach across the seam
+        // and for the bilinear fetch to take one texel beyond the face
+        v.fpad = v.kind == kCubeFace ? (x.k - 1) / 2 + 1 : 0;
+        v.fmap_off = fmaps;
+        {
+            const long long sp = x.resolution + 2LL * v.fpad;
+            fmaps += 2 * sp * sp;
+            if (v.kind == kCubeFace) {
+                v.pad_off = padmaps;          // relative; moved past the unpadded maps below
+                padmaps += 2 * sp * sp;
+                p->has_cube = true;
+                p->max_cube_padded = std::max(p->max_cube_padded, (int)(sp * sp));
+                p->max_cube_texels = std::max(p->max_cube_texels, x.resolution * x.resolution);
+                for (int e = 0; e < 4; ++e) v.cube_nb[e] = cube_edge_neighbour(x.cube_face, e);
+            }
+        }
         v.part_off = (int)part_light;
         part_light += (long long)v.tiles_x * v.tiles_y;
         v.part_gm_off = (int)part_gm;
@@ -274,6 +358,8 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->ntiles = (int)tiles;
     p->key_count = pix;
     p->map_floats = maps;
+    for (int l = 0; l < L; ++l)
+        if (p->views_h[l].fpad) p->views_h[l].pad_off += maps;
     p->image_floats = img;
     if (!layout_ok(clip) || !layout_ok(tri) || !layout_ok(tiles) || !layout_ok(pix) || !layout_ok(maps) ||
         !layout_ok(img) || !layout_ok((long long)bin_capacity_scale * (tri + tiles) / 4)) {
@@ -297,17 +383,26 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
             if (p->blur_groups.empty() || p->blur_groups.back().R != R)
                 p->blur_groups.push_back(dsm_plan::BlurGroup{R, q, 0, 0});
             dsm_plan::BlurGroup &g = p->blur_groups.back();
+            // forward: smoothed maps (cube faces: their padded copies) -> filtered maps
+            const ViewConst &v = p->views_h[l];
+            const int sp = x.resolution + 2 * v.fpad;
             BlurJob j;
             memset(&j, 0, sizeof(j));
-            j.S = x.resolution;
+            j.S = sp;
             j.k = x.k;
-            j.in_off = p->views_h[l].map_off;
-            j.out_off = p->views_h[l].map_off;
+            j.in_off = v.fpad ? v.pad_off : v.map_off;
+            j.out_off = v.fmap_off;
             j.tile_off = g.tiles;
-            j.tiles_x = blur_tiles_x(x.resolution);
+            j.tiles_x = blur_tiles_x(sp);
             filter_taps_host(x.filter, x.k, x.sigma, j.w);
-            g.tiles += blur_tiles(x.resolution, R);
+            g.tiles += blur_tiles(sp, R);
             g.n += 1;
+            p->blur_jobs_h.push_back(j);
+        }
+        // transpose: the same jobs reading the filtered side, writing the smoothed side
+        for (int q = 0; q < L; ++q) {
+            BlurJob j = p->blur_jobs_h[q];
+            std::swap(j.in_off, j.out_off);
             p->blur_jobs_h.push_back(j);
         }
     }
@@ -320,7 +415,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sv_sil = o; o = align_up(o + (size_t)tri);
     p->sv_tv = o; o = align_up(o + sizeof(TriVerts) * (size_t)std::max<long long>(Ft, 1));
     p->sv_F0 = o; o = align_up(o + 4 * (size_t)maps);
-    p->sv_M = o; o = align_up(o + 4 * (size_t)maps);
+    p->sv_M = o; o = align_up(o + 4 * (size_t)fmaps);
     p->sv_img0 = o; o = align_up(o + 4 * (size_t)img);
     p->saved_bytes = std::max<size_t>(o, kAlign);
     // scratch layout
@@ -338,14 +433,14 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_bin_pair = o; o = align_up(o + 4 * (size_t)p->capacity);
     p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
     p->sc_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
-    p->sc_F1 = o; o = align_up(o + 4 * (size_t)maps);
+    p->sc_F1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
     p->sc_gimg0 = o; o = align_up(o + 4 * (size_t)img);
     p->sc_bigcount = o; o = align_up(o + 64);
-    p->sc_gM = o; o = align_up(o + 4 * (size_t)maps);
+    p->sc_gM = o; o = align_up(o + 4 * (size_t)fmaps);
     p->sc_gclip = o; o = align_up(o + 16 * (size_t)clip);
     p->sc_zero_bwd_end = o;
     p->sc_glight = o; o = align_up(o + 4 * 24 * (size_t)std::max(L, 1));
-    p->sc_gF1 = o; o = align_up(o + 4 * (size_t)maps);
+    p->sc_gF1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
     p->sc_pair_sums = o; o = align_up(o + 4 * 21 * (size_t)p->capacity);
     p->sc_gtri = o; o = align_up(o + 4 * 21 * ((size_t)tri + 1));
     p->sc_biglist = o; o = align_up(o + 4 * ((size_t)tri + 1));
@@ -517,6 +612,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, silm,
                               verts, keys, F0, F1, 2, s));
     DSM_MARK(DSM_STAGE_FILTER);
+    if (p->has_cube) DSM_TRY(launch_cube_pad(p->views_d, p->L, p->max_cube_padded, F1, s));
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, F1, Mm, false, g.R, s));
     DSM_MARK(DSM_STAGE_LOOKUP);
@@ -573,7 +669,8 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
                                    bin_pair, pair_flag, pair_sums, gtri, part_render, p->C, jac, s));
     DSM_MARK(DSM_STAGE_FILTER_ADJ);
     for (const auto &g : p->blur_groups)
-        DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
+        DSM_TRY(launch_blur(p->blur_jobs_d + p->L + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
+    if (p->has_cube) DSM_TRY(launch_cube_pad_transpose(p->views_d, p->L, p->max_cube_texels, gF1, s));
     DSM_MARK(DSM_STAGE_LIGHT_ADJ);
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
                                   tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,
@@ -736,8 +833,19 @@ extern "C" dsm_status dsm_get_light_maps(const dsm_plan *p, const void *saved, c
     const ViewConst &v = p->views_h[light];
     const size_t base = which == 0 ? p->sv_F0 : which == 1 ? p->sc_F1 : p->sv_M;
     const void *src = which == 1 ? scratch : saved;
-    DSM_TRY(hipMemcpyAsync(out, at<char>(src, base + 4 * (size_t)v.map_off), 8 * (size_t)v.W * v.W,
-                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    if (which == 2 && v.fpad) {
+        // the face itself, without the texels copied from its neighbours
+        const size_t sp = (size_t)v.W + 2 * (size_t)v.fpad;
+        for (int c = 0; c < 2; ++c)
+            DSM_TRY(hipMemcpy2DAsync(out + (size_t)c * v.W * v.W, 4 * (size_t)v.W,
+                                     at<char>(src, base + 4 * ((size_t)v.fmap_off + c * sp * sp +
+                                                                (size_t)v.fpad * sp + v.fpad)),
+                                     4 * sp, 4 * (size_t)v.W, (size_t)v.W, hipMemcpyDeviceToDevice,
+                                     (hipStream_t)stream));
+        return DSM_OK;
+    }
+    DSM_TRY(hipMemcpyAsync(out, at<char>(src, base + 4 * (size_t)(which == 2 ? v.fmap_off : v.map_off)),
+                           8 * (size_t)v.W * v.W, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return DSM_OK;
 }
 

@@ -43,6 +43,11 @@ struct ViewConst {
     int cube_face;      // cube-face lights: face 0..5 (+x, -x, +y, -y, +z, -z)
     float warp_c;       // light views: exponential maps store exp(c z), exp(2 c z); 0 = plain z, z^2
     float bleed;        // light views: light-bleeding reduction amount
+    long long fmap_off; // light views: first texel of the filtered maps (and their gradient), side W + 2 fpad
+    long long pad_off;  // cube faces: first texel of the padded unfiltered maps in the smoothed-map buffers
+    int fpad;           // cube faces: texels of padding copied from the neighbouring faces; else 0
+    int cube_nb[4];     // cube faces, per map edge (left, right, top, bottom): neighbour face
+                        // | its edge << 3 | (indices along the edge reversed) << 5
 };
 
 // Receiver depth as the lookup compares it, and the variance floor:
@@ -271,6 +276,8 @@ hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntile
                          const unsigned *tile_start, const unsigned *bins, const unsigned *overflow_list,
                          const DevCounters *counters_ro, DevCounters *counters, unsigned long long *keys,
                          hipStream_t s);
+hipError_t launch_cube_pad(const ViewConst *views, int L, int max_padded, float *F1, hipStream_t s);
+hipError_t launch_cube_pad_transpose(const ViewConst *views, int L, int max_texels, float *gF1, hipStream_t s);
 hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const TriVerts *tv,
                           const unsigned long long *keys, float *F0, hipStream_t s);
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,

@@ -407,21 +407,24 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         // outside its own directions a cube face adds nothing, nor any gradient
         if (l.kind == kCubeFace && cube_face_of(x - l.pos[0], y - l.pos[1], z - l.pos[2]) != l.cube_face) continue;
         const int S = l.W;
-        const float *ma = maps + l.map_off, *mb = maps + l.map_off + (long long)S * S;
+        // filtered maps are stored with side Sp; cube faces keep P texels of
+        // their neighbours around the face, so taps may cross the seam
+        const int P = l.fpad, Sp = S + 2 * P;
+        const float *ma = maps + l.fmap_off, *mb = maps + l.fmap_off + (long long)Sp * Sp;
         if (inside) {
             const float sx = (ux + 1.f) * (0.5f * S) - 0.5f;
             const float sy = (1.f - uy) * (0.5f * S) - 0.5f;
             const float fx0 = floorf(sx), fy0 = floorf(sy);
             fx = sx - fx0;
             fy = sy - fy0;
-            const int ix = (int)fx0, iy = (int)fy0;
+            const int ix = (int)fx0 + P, iy = (int)fy0 + P;
             ixs = ix;
             iys = iy;
-            const int x0 = min(max(ix, 0), S - 1), x1 = min(max(ix + 1, 0), S - 1);
-            const int y0 = min(max(iy, 0), S - 1), y1 = min(max(iy + 1, 0), S - 1);
+            const int x0 = min(max(ix, 0), Sp - 1), x1 = min(max(ix + 1, 0), Sp - 1);
+            const int y0 = min(max(iy, 0), Sp - 1), y1 = min(max(iy + 1, 0), Sp - 1);
             const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
-            o00 = (long long)y0 * S + x0; o01 = (long long)y0 * S + x1;
-            o10 = (long long)y1 * S + x0; o11 = (long long)y1 * S + x1;
+            o00 = (long long)y0 * Sp + x0; o01 = (long long)y0 * Sp + x1;
+            o10 = (long long)y1 * Sp + x0; o11 = (long long)y1 * Sp + x1;
             m1 = ((w00 * ma[o00] + w01 * ma[o01]) + w10 * ma[o10]) + w11 * ma[o11];
             m2 = ((w00 * mb[o00] + w01 * mb[o01]) + w10 * mb[o10]) + w11 * mb[o11];
             float depth;
@@ -510,7 +513,7 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             }
             // bilinear scatter to the moment maps
             if (DIRECT) {
-                float *ga = gmaps + l.map_off, *gb = gmaps + l.map_off + (long long)S * S;
+                float *ga = gmaps + l.fmap_off, *gb = gmaps + l.fmap_off + (long long)Sp * Sp;
                 const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
                 atomic_add_f32(ga + o00, gm1 * w00); atomic_add_f32(ga + o01, gm1 * w01);
                 atomic_add_f32(ga + o10, gm1 * w10); atomic_add_f32(ga + o11, gm1 * w11);
@@ -699,7 +702,7 @@ __device__ __forceinline__ void lookup_backward_body(
                 MapHit hq[TS::PPT];
 #pragma unroll
                 for (int k = 0; k < TS::PPT; ++k) hq[k] = hits[k][q];
-                map_window_scatter<TS::NW, TS::PPT, (T == 32 ? 32 : 16)>(hq, l.W, gmaps + l.map_off);
+                map_window_scatter<TS::NW, TS::PPT, (T == 32 ? 32 : 16)>(hq, l.W + 2 * l.fpad, gmaps + l.fmap_off);
             }
         }
         const int ntiles = cv.tiles_x * cv.tiles_y;

@@ -28,7 +28,9 @@ struct dsm_plan {
     std::vector<int> render_lights_h;
     std::vector<int> vert_off, face_off, pose_counts;
     std::vector<float> pose_centers;
-    std::vector<dsm::BlurJob> blur_jobs_h;   // sorted by filter radius
+    std::vector<dsm::BlurJob> blur_jobs_h;   // sorted by filter radius; [0, L): forward, [L, 2L): transpose
+    bool has_cube = false;
+    int max_cube_padded = 0, max_cube_texels = 0;
     struct BlurGroup {
         int R, first, n, tiles;
     };

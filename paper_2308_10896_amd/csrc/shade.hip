@@ -135,12 +135,17 @@ struct Fetch {
     float fx, fy;
 };
 
-__device__ __forceinline__ Fetch bilinear2(const float *__restrict__ maps, long long off, int S, float sx, float sy) {
+// Bilinear fetch of both moments at (sx, sy) (texel centres at integers) from
+// maps of side S whose texel (0, 0) sits P texels inside the stored side
+// S + 2P (P > 0: cube faces padded from their neighbours), clamp-to-edge.
+__device__ __forceinline__ Fetch bilinear2(const float *__restrict__ maps, long long off, int S, int P, float sx,
+                                           float sy) {
     Fetch f;
     const float fx0 = floorf(sx), fy0 = floorf(sy);
     f.fx = sx - fx0;
     f.fy = sy - fy0;
-    const int ix = (int)fx0, iy = (int)fy0;
+    const int ix = (int)fx0 + P, iy = (int)fy0 + P;
+    S += 2 * P;
     f.x0 = min(max(ix, 0), S - 1);
     f.x1 = min(max(ix + 1, 0), S - 1);
     f.y0 = min(max(iy, 0), S - 1);
@@ -203,7 +208,7 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
             const int S = l.W;
             const float sx = (ux + 1.f) * (0.5f * S) - 0.5f;
             const float sy = (1.f - uy) * (0.5f * S) - 0.5f;
-            const Fetch m = bilinear2(maps, l.map_off, S, sx, sy);
+            const Fetch m = bilinear2(maps, l.fmap_off, S, l.fpad, sx, sy);
             float zw, floor_v;
             warp_receiver(l, light_depth(l, x, y, z), zw, floor_v);
             const float var = fmaxf(m.m2 - m.m1 * m.m1, floor_v);

@@ -112,3 +112,27 @@ def test_cube_face_light_validation_on_host():
         bd.desc.lights[2].type = typ
         h = C.c_void_p()
         assert lib.dsm_plan_create(C.byref(bd.desc), 0, 0, C.byref(h)) == 1
+
+
+def test_cube_group_validation_on_host():
+    """The six faces of a cube light must be consecutive lights with faces
+    0..5 and one map size and filter; a broken group is rejected before any
+    device call."""
+    import scenegen as sg
+    from paper_2308_10896_amd import _lib
+    lib = _lib.lib()
+
+    def create(mutate):
+        b = sg.cube_light_scene(resolution=32, view=32)
+        mutate(b)
+        bd = dsm._BatchDesc(b)
+        h = C.c_void_p()
+        return lib.dsm_plan_create(C.byref(bd.desc), 0, 0, C.byref(h))
+
+    def five(b):
+        b.lights.pop()
+        b.renders[0].lights = list(range(5))
+    assert create(five) == 1                                                       # five faces
+    assert create(lambda b: setattr(b.lights[3], 'resolution', 64)) == 1          # mixed sizes
+    assert create(lambda b: setattr(b.lights[4], 'k', 3)) == 1                     # mixed filters
+    assert create(lambda b: b.lights.__setitem__(slice(0, 2), b.lights[1::-1])) == 1   # out of order
