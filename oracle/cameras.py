@@ -156,38 +156,45 @@ def cube_edge_table():
 
 @functools.lru_cache(maxsize=16)
 def cube_pad_sources(S, P):
-    """For each face f, the (6 S S)-flat index of the texel every position of
-    its map padded by P texels copies: itself inside; across an edge, the
-    neighbouring face's texel at depth k - 1 from the shared edge for the
-    k-th padded texel, at the matching position along the edge; in a corner
-    block, the face's own corner texel.  Returns (6, S + 2P, S + 2P)."""
+    """What every position of a cube face's map padded by P texels reads, as
+    four (6 S S)-flat texel indices and their weights, each (6, S + 2P,
+    S + 2P, 4): inside the face, the texel itself; in an edge block, the
+    bilinear sample (clamp-to-edge) of the neighbouring face's map along the
+    direction the padded texel centre looks along when the face's plane is
+    continued across the edge; in a corner block, which no face covers, the
+    face's own corner texel."""
     tab = cube_edge_table()
     Sp = S + 2 * P
-    out = np.zeros((6, Sp, Sp), np.int64)
+    idx = np.zeros((6, Sp, Sp, 4), np.int64)
+    wgt = np.zeros((6, Sp, Sp, 4))
     for f in range(6):
+        a, s, u = cube_face_basis(f)
         for pj in range(Sp):
             for pi in range(Sp):
                 i, j = pi - P, pj - P
                 ins_i, ins_j = 0 <= i < S, 0 <= j < S
-                if ins_i and ins_j:
-                    g, jj, ii = f, j, i
-                elif not ins_i and not ins_j:
-                    g, jj, ii = f, min(max(j, 0), S - 1), min(max(i, 0), S - 1)
-                else:
-                    if i < 0:
-                        e, k, t = 0, -i, j
-                    elif i >= S:
-                        e, k, t = 1, i - S + 1, j
-                    elif j < 0:
-                        e, k, t = 2, -j, i
-                    else:
-                        e, k, t = 3, j - S + 1, i
-                    g, e2, flip = tab[f][e]
-                    t2 = S - 1 - t if flip else t
-                    dpt = k - 1
-                    jj, ii = ((t2, dpt), (t2, S - 1 - dpt), (dpt, t2), (S - 1 - dpt, t2))[e2]
-                out[f, pj, pi] = (g * S + jj) * S + ii
-    return out
+                if ins_i == ins_j:
+                    ii, jj = min(max(i, 0), S - 1), min(max(j, 0), S - 1)
+                    idx[f, pj, pi] = (f * S + jj) * S + ii
+                    wgt[f, pj, pi, 0] = 1.0
+                    continue
+                e = 0 if i < 0 else 1 if i >= S else 2 if j < 0 else 3
+                g = tab[f][e][0]
+                d = a + ((2 * i + 1) / S - 1) * s + (1 - (2 * j + 1) / S) * u
+                ag, sg, ug = cube_face_basis(g)
+                ug_ndc, vg_ndc = (d @ sg) / (d @ ag), (d @ ug) / (d @ ag)
+                sx = (ug_ndc + 1) * S / 2 - 0.5
+                sy = (1 - vg_ndc) * S / 2 - 0.5
+                x0, y0 = math.floor(sx), math.floor(sy)
+                fx, fy = sx - x0, sy - y0
+                xs = [min(max(x0, 0), S - 1), min(max(x0 + 1, 0), S - 1)]
+                ys = [min(max(y0, 0), S - 1), min(max(y0 + 1, 0), S - 1)]
+                taps = [(ys[0], xs[0], (1 - fx) * (1 - fy)), (ys[0], xs[1], fx * (1 - fy)),
+                        (ys[1], xs[0], (1 - fx) * fy), (ys[1], xs[1], fx * fy)]
+                for q, (yy, xx, w) in enumerate(taps):
+                    idx[f, pj, pi, q] = (g * S + yy) * S + xx
+                    wgt[f, pj, pi, q] = w
+    return idx, wgt
 
 
 def light_frame(light, param):

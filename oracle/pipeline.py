@@ -277,17 +277,20 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
         ls = lights[li]
         if L.kind == 'cubeface':
             # the six faces of one cube are consecutive lights; each face's
-            # map is padded from its neighbours across the cube's edges before
-            # filtering, so filter and fetch continue across the seams
+            # map is padded with bilinear samples of its neighbours across the
+            # cube's edges before filtering, so filter and fetch continue
+            # across the seams
             base = li - L.face
             group = batch.lights[base:base + 6]
             assert [q.face for q in group] == list(range(6)) and all(q.kind == 'cubeface' for q in group)
             assert all((q.resolution, q.k, q.filter, q.sigma) == (L.resolution, L.k, L.filter, L.sigma) for q in group)
             S = L.resolution
             P = (L.k - 1) // 2 + 1
-            src = cameras.cube_pad_sources(S, P)[L.face]
+            idx, wgt = cameras.cube_pad_sources(S, P)
             stack = torch.stack([lights[base + g]['F1'] for g in range(6)], 1).reshape(2, 6 * S * S)
-            Fp = stack[:, torch.as_tensor(src.ravel())].reshape(2, S + 2 * P, S + 2 * P)
+            taps = [stack[:, torch.as_tensor(idx[L.face, ..., q].ravel())] * torch.as_tensor(wgt[L.face, ..., q].ravel())
+                    for q in range(4)]
+            Fp = (((taps[0] + taps[1]) + taps[2]) + taps[3]).reshape(2, S + 2 * P, S + 2 * P)
             Mp = filter_separable(Fp, ls['taps'])
             ls.update(pad=P, Mpad=Mp, M=Mp[:, P:P + S, P:P + S])
         else:
