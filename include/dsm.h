@@ -92,9 +92,11 @@ typedef struct dsm_plan dsm_plan;
  *                in order and equal scene, resolution, filter, k and sigma
  *                (else DSM_ERR_INVALID_ARG); their parameters should hold
  *                the same position.  Each face's map is padded with
- *                (k - 1) / 2 + 1 texels copied from its neighbours across
- *                the cube's edges before filtering, so the filter and the
- *                bilinear fetch continue across the seams.
+ *                (k - 1) / 2 + 1 texels sampled from its neighbours across
+ *                the cube's edges (bilinear, along the direction of each
+ *                padded texel with the face's plane continued) before
+ *                filtering, so the filter and the bilinear fetch continue
+ *                across the seams.
  * Depths are stored as z = d / zfar.  `k` is the odd filter size of the
  * moment filter (box or Gaussian with std. dev. sigma in texels; sigma <= 0
  * means (k-1)/3).  min_variance floors sigma^2 = m2 - m1^2.

@@ -35,6 +35,45 @@ void cube_frame(int f, int a[3], int r[3], int u[3]) {
 
 int dot3i(const int x[3], const int y[3]) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; }
 
+// Bilinear taps for the padding of cube face f (side S, P texels): for edge
+// e, depth k = 1..P beyond it and position t along it, the padded texel
+// centre's direction a + u r + v up (u, v its NDC continued past +-1) is
+// projected into the neighbouring face g and sampled there with
+// clamp-to-edge, in double precision.
+void cube_ring_taps(int f, int S, int P, const int nb[4], std::vector<CubeTap> &out) {
+    int a[3], r[3], u[3];
+    cube_frame(f, a, r, u);
+    for (int e = 0; e < 4; ++e)
+        for (int k = 1; k <= P; ++k)
+            for (int t = 0; t < S; ++t) {
+                const int i = e == 0 ? -k : e == 1 ? S - 1 + k : t;
+                const int j = e == 2 ? -k : e == 3 ? S - 1 + k : t;
+                const double un = (double)(2 * i + 1) / S - 1.0, vn = 1.0 - (double)(2 * j + 1) / S;
+                double d[3];
+                for (int c = 0; c < 3; ++c) d[c] = a[c] + un * r[c] + vn * u[c];
+                CubeTap tp;
+                tp.g = nb[e] & 7;
+                int ag[3], rg[3], ug[3];
+                cube_frame(tp.g, ag, rg, ug);
+                const double da = d[0] * ag[0] + d[1] * ag[1] + d[2] * ag[2];
+                const double gu = (d[0] * rg[0] + d[1] * rg[1] + d[2] * rg[2]) / da;
+                const double gv = (d[0] * ug[0] + d[1] * ug[1] + d[2] * ug[2]) / da;
+                const double sx = (gu + 1.0) * S / 2.0 - 0.5, sy = (1.0 - gv) * S / 2.0 - 0.5;
+                const double x0 = floor(sx), y0 = floor(sy), fx = sx - x0, fy = sy - y0;
+                const int xs[2] = {std::min(std::max((int)x0, 0), S - 1), std::min(std::max((int)x0 + 1, 0), S - 1)};
+                const int ys[2] = {std::min(std::max((int)y0, 0), S - 1), std::min(std::max((int)y0 + 1, 0), S - 1)};
+                tp.o[0] = ys[0] * S + xs[0];
+                tp.o[1] = ys[0] * S + xs[1];
+                tp.o[2] = ys[1] * S + xs[0];
+                tp.o[3] = ys[1] * S + xs[1];
+                tp.w[0] = (float)((1.0 - fx) * (1.0 - fy));
+                tp.w[1] = (float)(fx * (1.0 - fy));
+                tp.w[2] = (float)((1.0 - fx) * fy);
+                tp.w[3] = (float)(fx * fy);
+                out.push_back(tp);
+            }
+}
+
 // The face across edge e (0 left, 1 right, 2 top, 3 bottom of the map) of
 // cube face f, the edge of that face's map on the same cube edge, and whether
 // texel indices along the edge run in opposite directions: packed as
@@ -280,6 +319,9 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
                 p->max_cube_padded = std::max(p->max_cube_padded, (int)(sp * sp));
                 p->max_cube_texels = std::max(p->max_cube_texels, x.resolution * x.resolution);
                 for (int e = 0; e < 4; ++e) v.cube_nb[e] = cube_edge_neighbour(x.cube_face, e);
+                v.ring_off = (int)p->cube_taps_h.size();
+                cube_ring_taps(x.cube_face, x.resolution, v.fpad, v.cube_nb, p->cube_taps_h);
+                p->max_cube_ring = std::max(p->max_cube_ring, 4 * v.fpad * x.resolution);
             }
         }
         v.part_off = (int)part_light;
@@ -512,6 +554,8 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     if (st == DSM_OK) st = upload(&p->adj_d, adj.data(), adj.size());
     if (st == DSM_OK) st = upload(&p->tile_view_d, tile_view.data(), tile_view.size());
     if (st == DSM_OK) st = upload(&p->blur_jobs_d, p->blur_jobs_h.data(), p->blur_jobs_h.size());
+    if (st == DSM_OK && !p->cube_taps_h.empty())
+        st = upload(&p->cube_taps_d, p->cube_taps_h.data(), p->cube_taps_h.size());
     if (st == DSM_OK) st = upload(&p->scene_vert_off_d, p->vert_off.data(), p->vert_off.size());
     if (st == DSM_OK) st = upload(&p->pose_counts_d, p->pose_counts.data(), p->pose_counts.size());
     if (st == DSM_OK) st = upload(&p->pose_centers_d, p->pose_centers.data(), p->pose_centers.size());
@@ -528,7 +572,7 @@ extern "C" void dsm_plan_destroy(dsm_plan *p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *bufs[] = {p->views_d, p->light_cams_d, p->renders_d, p->render_lights_d, p->faces_d, p->adj_d,
-                    p->tile_view_d, p->blur_jobs_d, p->scene_vert_off_d, p->pose_counts_d, p->pose_centers_d,
+                    p->tile_view_d, p->blur_jobs_d, p->cube_taps_d, p->scene_vert_off_d, p->pose_counts_d, p->pose_centers_d,
                     p->cam_renders_off_d, p->cam_renders_d, p->scene_views_off_d, p->scene_views_d, p->vc_off_d,
                     p->vc_list_d, p->light_renders_off_d, p->light_renders_d, p->scene_face_off_d};
     for (void *b : bufs)
@@ -612,7 +656,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, silm,
                               verts, keys, F0, F1, 2, s));
     DSM_MARK(DSM_STAGE_FILTER);
-    if (p->has_cube) DSM_TRY(launch_cube_pad(p->views_d, p->L, p->max_cube_padded, F1, s));
+    if (p->has_cube) DSM_TRY(launch_cube_pad(p->views_d, p->L, p->max_cube_padded, p->cube_taps_d, F1, s));
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + g.first, g.n, g.tiles, F1, Mm, false, g.R, s));
     DSM_MARK(DSM_STAGE_LOOKUP);
@@ -670,7 +714,9 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_MARK(DSM_STAGE_FILTER_ADJ);
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + p->L + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
-    if (p->has_cube) DSM_TRY(launch_cube_pad_transpose(p->views_d, p->L, p->max_cube_texels, gF1, s));
+    if (p->has_cube)
+        DSM_TRY(launch_cube_pad_transpose(p->views_d, p->L, p->max_cube_texels, p->max_cube_ring, p->cube_taps_d,
+                                          gF1, s));
     DSM_MARK(DSM_STAGE_LIGHT_ADJ);
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
                                   tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,

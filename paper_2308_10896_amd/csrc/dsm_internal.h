@@ -45,9 +45,20 @@ struct ViewConst {
     float bleed;        // light views: light-bleeding reduction amount
     long long fmap_off; // light views: first texel of the filtered maps (and their gradient), side W + 2 fpad
     long long pad_off;  // cube faces: first texel of the padded unfiltered maps in the smoothed-map buffers
-    int fpad;           // cube faces: texels of padding copied from the neighbouring faces; else 0
+    int fpad;           // cube faces: texels of padding sampled from the neighbouring faces; else 0
     int cube_nb[4];     // cube faces, per map edge (left, right, top, bottom): neighbour face
                         // | its edge << 3 | (indices along the edge reversed) << 5
+    int ring_off;       // cube faces: first CubeTap of this face's padding (4 P S entries)
+};
+
+// One padded texel of a cube face beyond one of its edges: the bilinear
+// sample of the neighbouring face g along the direction the padded texel
+// centre looks along.  Entries of a face run over edge e (left, right, top,
+// bottom), depth k = 1..P beyond it, and position t = 0..S-1 along it.
+struct CubeTap {
+    int g;                        // neighbouring face 0..5
+    int o[4];                     // texel indices j * S + i of the taps in g's map
+    float w[4];                   // bilinear weights (clamp-to-edge taps)
 };
 
 // Receiver depth as the lookup compares it, and the variance floor:
@@ -276,8 +287,10 @@ hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntile
                          const unsigned *tile_start, const unsigned *bins, const unsigned *overflow_list,
                          const DevCounters *counters_ro, DevCounters *counters, unsigned long long *keys,
                          hipStream_t s);
-hipError_t launch_cube_pad(const ViewConst *views, int L, int max_padded, float *F1, hipStream_t s);
-hipError_t launch_cube_pad_transpose(const ViewConst *views, int L, int max_texels, float *gF1, hipStream_t s);
+hipError_t launch_cube_pad(const ViewConst *views, int L, int max_padded, const CubeTap *taps, float *F1,
+                           hipStream_t s);
+hipError_t launch_cube_pad_transpose(const ViewConst *views, int L, int max_texels, int max_ring,
+                                     const CubeTap *taps, float *gF1, hipStream_t s);
 hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const TriVerts *tv,
                           const unsigned long long *keys, float *F0, hipStream_t s);
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,

@@ -30,7 +30,8 @@ struct dsm_plan {
     std::vector<float> pose_centers;
     std::vector<dsm::BlurJob> blur_jobs_h;   // sorted by filter radius; [0, L): forward, [L, 2L): transpose
     bool has_cube = false;
-    int max_cube_padded = 0, max_cube_texels = 0;
+    int max_cube_padded = 0, max_cube_texels = 0, max_cube_ring = 0;
+    std::vector<dsm::CubeTap> cube_taps_h;
     struct BlurGroup {
         int R, first, n, tiles;
     };
@@ -45,6 +46,7 @@ struct dsm_plan {
     int *adj_d = nullptr;
     int *tile_view_d = nullptr;
     dsm::BlurJob *blur_jobs_d = nullptr;
+    dsm::CubeTap *cube_taps_d = nullptr;
     int *scene_vert_off_d = nullptr;    // [B+1]
     int *pose_counts_d = nullptr;       // [B]
     float *pose_centers_d = nullptr;    // [B,3]

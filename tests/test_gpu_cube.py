@@ -29,8 +29,9 @@ def check_forward(b, g, o):
         assert_close(f'F0[{l}]', g['F0'][l], o['F0'][l], MAP_RTOL, MAP_ATOL)
         assert_close(f'F1[{l}]', g['F1'][l], o['F1'][l], MAP_RTOL, MAP_ATOL)
         assert_close(f'M[{l}]', g['M'][l], o['M'][l], MAP_RTOL, MAP_ATOL)
-    # the +y face sees nothing: its maps hold the far value everywhere
-    assert np.all(g['M'][2] == 1.0)
+    # the +y face sees nothing: its maps hold the far value everywhere (to
+    # the rounding of the float32 bilinear weights of its padding)
+    assert np.allclose(g['M'][2], 1.0, rtol=0, atol=1e-6)
     for r in range(len(b.renders)):
         # face choice within a 1e-4 relative gap of the two largest |d_a| is a tie
         ok = ~cone_ambiguous(b, o, r, margin=1e-4)[..., None]
