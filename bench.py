@@ -39,14 +39,14 @@ HBM_PEAK_GBS = 8000.0
 PMC_FETCH_SCALE = 131072.0 / 65548.0
 PMC_WRITE_SCALE = 131072.0 / 131072.0
 PMC_TRAFFIC = {
-    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65872.4, write_kib=131072.0,
-                   sources=('blur.hip', 'dsm_internal.h'), sha1='f17783d6cf3ee46d'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65702.5, write_kib=131072.0,
-                       sources=('blur.hip', 'dsm_internal.h'), sha1='f17783d6cf3ee46d'),
-    'lookup': dict(kernel='lookup_kernel', fetch_kib=158567.9, write_kib=65536.0,
-                   sources=('shade.hip', 'dsm_internal.h'), sha1='9e1804da52f8e887'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=120412.7, write_kib=93617.2,
-                       sources=('grad.hip', 'dsm_internal.h'), sha1='6bfdf497d2a510c1'),
+    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65876.1, write_kib=131072.0,
+                   sources=('blur.hip', 'dsm_internal.h'), sha1='484224a809f695cf'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65699.4, write_kib=131072.0,
+                       sources=('blur.hip', 'dsm_internal.h'), sha1='484224a809f695cf'),
+    'lookup': dict(kernel='lookup_kernel', fetch_kib=158568.0, write_kib=65536.0,
+                   sources=('shade.hip', 'dsm_internal.h'), sha1='449fe437f7d52725'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=120412.9, write_kib=93632.1,
+                       sources=('grad.hip', 'dsm_internal.h'), sha1='19cdb5e922ba9ad8'),
 }
 
 
