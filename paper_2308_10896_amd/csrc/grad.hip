@@ -61,6 +61,15 @@ __device__ __forceinline__ void wave_add(const float (&val)[N], float *dst) {
 
 __device__ __forceinline__ float ndc_c(int i, int n) { return (float)(2 * i + 1) / (float)n - 1.0f; }
 
+// Reciprocal (about one ulp) for quotients that only scale a gradient term:
+// the correctly rounded division the rest of the library uses (for the
+// quantities that decide coverage, cells and branches) costs about ten
+// instructions, this one.
+__device__ __forceinline__ float grcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Barycentrics through the hardware reciprocal of their sum (about one ulp):
+// the forward lookup forms the world point the same way, so the reverse pass
+// recomputes its values, and its decisions, bit for bit.
 struct BaryFull {
     float a0x, a0y, a1x, a1y, a2x, a2y, k0, k1, k2, s, b0, b1, b2;
 };
@@ -74,7 +83,8 @@ __device__ __forceinline__ BaryFull bary_full(float4 c0, float4 c1, float4 c2, f
     r.k1 = r.a2x * r.a0y - r.a2y * r.a0x;
     r.k2 = r.a0x * r.a1y - r.a0y * r.a1x;
     r.s = r.k0 + r.k1 + r.k2;
-    r.b0 = r.k0 / r.s; r.b1 = r.k1 / r.s; r.b2 = r.k2 / r.s;
+    const float rs = __builtin_amdgcn_rcpf(r.s);
+    r.b0 = r.k0 * rs; r.b1 = r.k1 * rs; r.b2 = r.k2 * rs;
     return r;
 }
 
@@ -82,7 +92,8 @@ __device__ __forceinline__ BaryFull bary_full(float4 c0, float4 c1, float4 c2, f
 __device__ __forceinline__ void bary_backward(const BaryFull &b, float px, float py, float gb0, float gb1, float gb2,
                                               float out[9]) {
     const float dotg = (gb0 * b.b0 + gb1 * b.b1) + gb2 * b.b2;
-    const float gk0 = (gb0 - dotg) / b.s, gk1 = (gb1 - dotg) / b.s, gk2 = (gb2 - dotg) / b.s;
+    const float rs = grcp(b.s);
+    const float gk0 = (gb0 - dotg) * rs, gk1 = (gb1 - dotg) * rs, gk2 = (gb2 - dotg) * rs;
     const float ga0x = -gk1 * b.a2y + gk2 * b.a1y, ga0y = gk1 * b.a2x - gk2 * b.a1x;
     const float ga1x = gk0 * b.a2y - gk2 * b.a0y, ga1y = -gk0 * b.a2x + gk2 * b.a0x;
     const float ga2x = -gk0 * b.a1y + gk1 * b.a0y, ga2y = gk0 * b.a1x - gk1 * b.a0x;
@@ -381,7 +392,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
     const float e2x = v2[0] - v0[0], e2y = v2[1] - v0[1], e2z = v2[2] - v0[2];
     const float crx = e1y * e2z - e1z * e2y, cry = e1z * e2x - e1x * e2z, crz = e1x * e2y - e1y * e2x;
     const float nn = sqrtf((crx * crx + cry * cry) + crz * crz);
-    const float nx = crx / nn, ny = cry / nn, nz = crz / nn;
+    const float rn0 = __builtin_amdgcn_rcpf(nn);
+    const float nx = crx * rn0, ny = cry * rn0, nz = crz * rn0;
     float rho[3] = {0.f, 0.f, 0.f};
     for (int c = 0; c < C; ++c) rho[c] = albedo[(size_t)(cv.face_off + tri) * C + c];
     float srho = 0.f;
@@ -396,7 +408,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         const float cx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
         const float cy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
         const float cw = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
-        const float ux = cx / cw, uy = cy / cw;
+        const float rcw = __builtin_amdgcn_rcpf(cw);
+        const float ux = cx * rcw, uy = cy * rcw;
         const bool inside = cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f;
         float vis = 1.f, visr = 1.f, zz = 0.f, zw = 0.f, floor_v = 0.f, m1 = 0.f, m2 = 0.f, var = 0.f, dd = 0.f,
               fx = 0.f, fy = 0.f;
@@ -470,7 +483,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             gdir[0] -= gox; gdir[1] -= goy; gdir[2] -= goz;
         } else {
             const float od = (ox * gox + oy * goy) + oz * goz;
-            const float gpx = (gox - ox * od) / olen, gpy = (goy - oy * od) / olen, gpz = (goz - oz * od) / olen;
+            const float rl = grcp(olen);
+            const float gpx = (gox - ox * od) * rl, gpy = (goy - oy * od) * rl, gpz = (goz - oz * od) * rl;
             gpos[0] += gpx; gpos[1] += gpy; gpos[2] += gpz;
             gx[0] -= gpx; gx[1] -= gpy; gx[2] -= gpz;
         }
@@ -481,12 +495,14 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             float dv_dmu, dv_dvar_raw;
             if (l.warp_c > 0.f) {
                 // exponential maps: the squares of var and dd overflow float32
-                const float tv = var / qd, td = dd / qd;
+                const float rq = grcp(qd);
+                const float tv = var * rq, td = dd * rq;
                 dv_dmu = 2.f * tv * td;
                 dv_dvar_raw = td * td;
             } else {
-                dv_dmu = 2.f * var * dd / (qd * qd);
-                dv_dvar_raw = dd * dd / (qd * qd);
+                const float rq2 = grcp(qd * qd);
+                dv_dmu = 2.f * var * dd * rq2;
+                dv_dvar_raw = dd * dd * rq2;
             }
             const bool clamped = m2 - m1 * m1 < floor_v;
             const float dv_dvar = clamped ? 0.f : dv_dvar_raw;
@@ -499,7 +515,7 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                 if (clamped) dv_dzw += dv_dvar_raw * (2.f * l.min_var * l.warp_c * l.warp_c * zw);
                 dv_dzw *= l.warp_c * zw;
             }
-            const float gdepth = gvr * dv_dzw / l.zfar;
+            const float gdepth = gvr * dv_dzw * grcp(l.zfar);
             if (l.kind == kDirectional) {
                 gx[0] += gdepth * l.dir[0]; gx[1] += gdepth * l.dir[1]; gx[2] += gdepth * l.dir[2];
                 gpos[0] -= gdepth * l.dir[0]; gpos[1] -= gdepth * l.dir[1]; gpos[2] -= gdepth * l.dir[2];
@@ -507,7 +523,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             } else {
                 const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
                 const float dl = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
-                const float ux_ = ddx / dl, uy_ = ddy / dl, uz_ = ddz / dl;
+                const float rd = grcp(dl);
+                const float ux_ = ddx * rd, uy_ = ddy * rd, uz_ = ddz * rd;
                 gx[0] += gdepth * ux_; gx[1] += gdepth * uy_; gx[2] += gdepth * uz_;
                 gpos[0] -= gdepth * ux_; gpos[1] -= gdepth * uy_; gpos[2] -= gdepth * uz_;
             }
@@ -530,9 +547,10 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             const float gsx = gm1 * dm1fx + gm2 * dm2fx;
             const float gsy = gm1 * dm1fy + gm2 * dm2fy;
             const float hs = 0.5f * S;
-            gcx = gsx * hs / cw;
-            gcy = -gsy * hs / cw;
-            gcw = (-gsx * hs * cx + gsy * hs * cy) / (cw * cw);
+            const float rw = grcp(cw);
+            gcx = gsx * hs * rw;
+            gcy = -gsy * hs * rw;
+            gcw = (-gsx * hs * cx + gsy * hs * cy) * (rw * rw);
             for (int k = 0; k < 3; ++k) gx[k] += (M[k] * gcx + M[4 + k] * gcy) + M[12 + k] * gcw;
         }
         // dL/dM = (gcx, gcy, 0, gcw) outer [x, 1]; with dL/dpos, dL/ddir through J
@@ -553,7 +571,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
     for (int c = 0; c < 3; ++c) vals[18 + c] = c < C ? g[c] * shade : 0.f;
     // normal: n = cr / |cr|, cr = e1 x e2
     const float ndg = (nx * gn[0] + ny * gn[1]) + nz * gn[2];
-    const float gcr[3] = {(gn[0] - nx * ndg) / nn, (gn[1] - ny * ndg) / nn, (gn[2] - nz * ndg) / nn};
+    const float rn = grcp(nn);
+    const float gcr[3] = {(gn[0] - nx * ndg) * rn, (gn[1] - ny * ndg) * rn, (gn[2] - nz * ndg) * rn};
     const float ge1[3] = {e2y * gcr[2] - e2z * gcr[1], e2z * gcr[0] - e2x * gcr[2], e2x * gcr[1] - e2y * gcr[0]};
     const float ge2[3] = {gcr[1] * e1z - gcr[2] * e1y, gcr[2] * e1x - gcr[0] * e1z, gcr[0] * e1y - gcr[1] * e1x};
     // x = sum b_i v_i
@@ -830,7 +849,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
             const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
             // F0 = (f, f^2), f = z, or exp(c z) for exponential maps
             const float gz = l.warp_c > 0.f ? l.warp_c * f0a[pp] * (g0 + 2.f * f0a[pp] * g1) : g0 + 2.f * f0a[pp] * g1;
-            const float gdepth = gz / l.zfar;
+            const float gdepth = gz * grcp(l.zfar);
             float gx[3];
             if (l.kind == kDirectional) {
                 gx[0] = gdepth * l.dir[0]; gx[1] = gdepth * l.dir[1]; gx[2] = gdepth * l.dir[2];
@@ -839,7 +858,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
             } else {
                 const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
                 const float dl = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
-                const float inv = gdepth / dl;
+                const float inv = gdepth * grcp(dl);
                 gx[0] = ddx * inv; gx[1] = ddy * inv; gx[2] = ddz * inv;
                 accl[0] -= gx[0]; accl[1] -= gx[1]; accl[2] -= gx[2];
             }

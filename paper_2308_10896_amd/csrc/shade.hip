@@ -38,6 +38,19 @@ __device__ __forceinline__ Bary persp_bary(float4 c0, float4 c1, float4 c2, floa
     return Bary{k0 / s, k1 / s, k2 / s};
 }
 
+// persp_bary with the hardware reciprocal of the sum (the lookup's form; its
+// adjoint recomputes the same values).
+__device__ __forceinline__ Bary persp_bary_rcp(float4 c0, float4 c1, float4 c2, float px, float py) {
+    const float a0x = c0.x - px * c0.w, a0y = c0.y - py * c0.w;
+    const float a1x = c1.x - px * c1.w, a1y = c1.y - py * c1.w;
+    const float a2x = c2.x - px * c2.w, a2y = c2.y - py * c2.w;
+    const float k0 = a1x * a2y - a1y * a2x;
+    const float k1 = a2x * a0y - a2y * a0x;
+    const float k2 = a0x * a1y - a0y * a1x;
+    const float rs = __builtin_amdgcn_rcpf(k0 + k1 + k2);
+    return Bary{k0 * rs, k1 * rs, k2 * rs};
+}
+
 __device__ __forceinline__ float ndc_centre(int i, int n) { return (float)(2 * i + 1) / (float)n - 1.0f; }
 
 __device__ __forceinline__ float light_depth(const ViewConst &l, float x, float y, float z) {
@@ -182,7 +195,7 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
     const float px = ndc_centre(i, W), py = -ndc_centre(j, H);
     const float4 c0 = clip_of(cv.M, v0[0], v0[1], v0[2]), c1 = clip_of(cv.M, v1[0], v1[1], v1[2]),
                  c2 = clip_of(cv.M, v2[0], v2[1], v2[2]);
-    const Bary b = persp_bary(c0, c1, c2, px, py);
+    const Bary b = persp_bary_rcp(c0, c1, c2, px, py);
     const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
     const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
     const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
@@ -190,9 +203,10 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
     const float e2x = v2[0] - v0[0], e2y = v2[1] - v0[1], e2z = v2[2] - v0[2];
     float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
     const float nn = sqrtf((nx * nx + ny * ny) + nz * nz);
-    nx /= nn;
-    ny /= nn;
-    nz /= nn;
+    const float rn = __builtin_amdgcn_rcpf(nn);
+    nx *= rn;
+    ny *= rn;
+    nz *= rn;
     float shade = 0.f;
     for (int q = 0; q < R.light_count; ++q) {
         const ViewConst &l = views[render_lights[R.light_begin + q]];
@@ -203,7 +217,8 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
         const float cy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
         const float cw = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
         float vis = 1.f;
-        const float ux = cx / cw, uy = cy / cw;
+        const float rcw = __builtin_amdgcn_rcpf(cw);
+        const float ux = cx * rcw, uy = cy * rcw;
         if (cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f) {
             const int S = l.W;
             const float sx = (ux + 1.f) * (0.5f * S) - 0.5f;

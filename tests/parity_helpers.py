@@ -13,6 +13,10 @@ from oracle import pipeline as P
 # variance floor).  Gradients: normwise per parameter group.
 MAP_RTOL, MAP_ATOL = 1e-4, 1e-6
 IMG_RTOL, IMG_ATOL = 1e-4, 1e-4
+# Pixels whose shadowed visibility rests on sigma^2 within 10x the variance
+# floor: float32 forms m2 - m1^2 with an absolute error e of a few 1e-8, which
+# moves v = s/(s + d^2) by up to e / (4 s), about 5e-4 at the floor.
+IMG_FLOOR_ATOL = 1e-3
 GRAD_TOL = 1e-3      # normwise relative, per parameter group
 
 
@@ -156,3 +160,33 @@ def decisions_clear(batch, oracle_res, render, cell_eps=1e-3, face_eps=1e-4, var
         if f['cone_margin'] is not None:
             ok[view['flat']] &= f['cone_margin'] >= face_eps
     return ok.reshape(cam.height, cam.width)
+
+
+def floor_conditioned(batch, oracle_res, render, ratio=10.0, dilate=0):
+    """Camera pixels whose visibility, in the shadowed branch of some light,
+    rests on sigma^2 within `ratio` times the variance floor (dilated by
+    `dilate` pixels, for images after the edge smoothing that blends
+    neighbours)."""
+    r = batch.renders[render]
+    cam = batch.cameras[r.camera]
+    m = np.zeros(cam.height * cam.width, bool)
+    view = oracle_res['raw']['views'][render]
+    for li, f in oracle_res['flags'][render].items():
+        if f['var_ratio'] is not None:
+            m[view['flat']] |= f['inside'] & ~f['branch'] & (f['var_ratio'] < ratio)
+    m = m.reshape(cam.height, cam.width)
+    for _ in range(dilate):
+        d = m.copy()
+        d[1:] |= m[:-1]; d[:-1] |= m[1:]; d[:, 1:] |= m[:, :-1]; d[:, :-1] |= m[:, 1:]
+        m = d
+    return m
+
+
+def assert_image(name, got, want, batch, oracle_res, render, mask=None, smoothed=False):
+    """Image parity: IMG_ATOL everywhere except at floor-conditioned pixels
+    (IMG_FLOOR_ATOL there), both with IMG_RTOL."""
+    cond = floor_conditioned(batch, oracle_res, render, dilate=1 if smoothed else 0)[..., None]
+    cond = np.broadcast_to(cond, np.shape(want))
+    base = np.ones(np.shape(want), bool) if mask is None else np.broadcast_to(mask, np.shape(want))
+    assert_close(name, got, want, IMG_RTOL, IMG_ATOL, mask=base & ~cond)
+    assert_close(name + ' (near the variance floor)', got, want, IMG_RTOL, IMG_FLOOR_ATOL, mask=base & cond)

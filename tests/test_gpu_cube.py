@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from parity_helpers import (GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous,
+from parity_helpers import (assert_image, GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous,
                             decisions_clear, gpu_run, loss_grad, normwise, oracle_run, random_grad)
 
 pytestmark = pytest.mark.gpu
@@ -36,8 +36,8 @@ def check_forward(b, g, o):
         # face choice within a 1e-4 relative gap of the two largest |d_a| is a tie
         ok = ~cone_ambiguous(b, o, r, margin=1e-4)[..., None]
         assert ok.mean() > 0.99
-        assert_close(f'img0[{r}]', g['img0'][r], o['img0'][r], IMG_RTOL, IMG_ATOL, mask=ok)
-        assert_close(f'image[{r}]', g['images'][r], o['images'][r], IMG_RTOL, IMG_ATOL, mask=ok)
+        assert_image(f'img0[{r}]', g['img0'][r], o['img0'][r], b, o, r, mask=ok)
+        assert_image(f'image[{r}]', g['images'][r], o['images'][r], b, o, r, mask=ok, smoothed=True)
     # triangles behind a face's light plane are dropped in that face alone
     assert g['stats']['culled'] == o['culled'] > 0
     assert g['stats']['bad_indices'] == 0

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from parity_helpers import (GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous,
+from parity_helpers import (assert_image, GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous,
                             decisions_clear, gpu_run, loss_grad, normwise, oracle_run, random_grad)
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +60,7 @@ def test_forward_matches_oracle(name):
         assert_close(f'M[{l}]', g['M'][l], o['M'][l], MAP_RTOL, MAP_ATOL)
     for r in range(len(b.renders)):
         ok = ~cone_ambiguous(b, o, r)[..., None]
-        assert_close(f'image[{r}]', g['images'][r], o['images'][r], IMG_RTOL, IMG_ATOL, mask=ok)
+        assert_image(f'image[{r}]', g['images'][r], o['images'][r], b, o, r, mask=ok, smoothed=True)
 
 
 @pytest.mark.parametrize('name', list(BATCHES))

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import scenegen as sg
-from parity_helpers import (GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, decisions_clear,
+from parity_helpers import (assert_image, GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, decisions_clear,
                             normwise, oracle_run, random_grad)
 
 pytestmark = pytest.mark.gpu
@@ -59,6 +59,6 @@ def test_full_size_batch_sampled_scenes():
         assert np.array_equal(plan.view_keys(saved, i).cpu().numpy().view(np.uint64), o['keys'][0])
         assert np.array_equal(plan.view_keys(saved, L + i).cpu().numpy().view(np.uint64), o['keys'][1])
         assert_close(f'M[{i}]', plan.light_maps(saved, scratch, i, 2).cpu().numpy(), o['M'][0], MAP_RTOL, MAP_ATOL)
-        assert_close(f'image[{i}]', imgs[i], o['images'][0], IMG_RTOL, IMG_ATOL)
+        assert_image(f'image[{i}]', imgs[i], o['images'][0], b1, o, 0, smoothed=True)
         normwise(f'gpose[{i}]', gpose[i], o['gpose'][0], GRAD_TOL)
         normwise(f'glight[{i}]', gl[i], o['glight'][0], GRAD_TOL)

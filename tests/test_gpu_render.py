@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from parity_helpers import (IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous, gpu_run,
+from parity_helpers import (assert_image, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous, gpu_run,
                             loss_grad, normwise, oracle_run, random_grad)
 
 pytestmark = pytest.mark.gpu
@@ -44,8 +44,8 @@ def check_forward(b, g, o):
         assert_close(f'M[{l}]', g['M'][l], o['M'][l], MAP_RTOL, MAP_ATOL)
     for r in range(len(b.renders)):
         ok = ~cone_ambiguous(b, o, r)[..., None]
-        assert_close(f'img0[{r}]', g['img0'][r], o['img0'][r], IMG_RTOL, IMG_ATOL, mask=ok)
-        assert_close(f'image[{r}]', g['images'][r], o['images'][r], IMG_RTOL, IMG_ATOL, mask=ok)
+        assert_image(f'img0[{r}]', g['img0'][r], o['img0'][r], b, o, r, mask=ok)
+        assert_image(f'image[{r}]', g['images'][r], o['images'][r], b, o, r, mask=ok, smoothed=True)
     assert g['stats']['culled'] == 0 and o['culled'] == 0
     assert g['stats']['bad_indices'] == 0
 
