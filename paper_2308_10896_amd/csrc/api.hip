@@ -481,7 +481,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_gM = o; o = align_up(o + 4 * (size_t)fmaps);
     p->sc_gclip = o; o = align_up(o + 16 * (size_t)clip);
     p->sc_zero_bwd_end = o;
-    p->sc_glight = o; o = align_up(o + 4 * 24 * (size_t)std::max(L, 1));
+    p->sc_glight = o; o = align_up(o + 4 * 3 * (size_t)kGlightBlocks * (size_t)std::max(L, 1));
     p->sc_gF1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
     p->sc_pair_sums = o; o = align_up(o + 4 * 21 * (size_t)p->capacity);
     p->sc_gtri = o; o = align_up(o + 4 * 21 * ((size_t)tri + 1));
@@ -729,7 +729,7 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
                                     big_count, verts, gclip, gverts, part_gm, galbedo, p->C, jac, s));
     DSM_MARK(DSM_STAGE_LIGHT_GRAD);
     DSM_TRY(launch_glight_reduce(p->views_d, p->L, p->renders_d, p->light_renders_off_d, p->light_renders_d, part_gm,
-                                 part_light, part_render, glparams, s));
+                                 part_light, part_render, at<float>(scratch, p->sc_glight), glparams, s));
     DSM_MARK(DSM_STAGE_COUNT);
     return DSM_OK;
 }

@@ -116,6 +116,9 @@ struct TriSetup {
 };
 static_assert(sizeof(TriSetup) == 64, "TriSetup must stay 64 bytes");
 
+// Workgroups per light in the first pass of the light-gradient reduction.
+constexpr int kGlightBlocks = 16;
+
 struct BlurJob {
     int S;
     int k;
@@ -330,7 +333,8 @@ hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max
 hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *counters, float *gtri, hipStream_t s);
 hipError_t launch_glight_reduce(const ViewConst *views, int L, const RenderConst *renders,
                                 const int *light_renders_off, const int *light_renders, const float *part_gm,
-                                const float *part_light, const float *part_render, float *gparams, hipStream_t s);
+                                const float *part_light, const float *part_render, float *gl_part, float *gparams,
+                                hipStream_t s);
 hipError_t launch_pose(const int *scene_vert_off, const int *pose_counts, const float *pose_centers, int B,
                        int max_verts, const float *local, const float *poses, float *world, hipStream_t s);
 hipError_t launch_pose_backward(const int *scene_vert_off, const int *pose_counts, int B, int max_verts,

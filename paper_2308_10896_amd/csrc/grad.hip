@@ -1030,24 +1030,28 @@ __global__ void albedo_gather_kernel(const ViewConst *__restrict__ views, int L,
 }
 
 // glight[l] = sum of every partial written for light l (vertex blocks, light
-// tiles, and the tiles of each render that uses it).
-__global__ __launch_bounds__(256) void glight_reduce_kernel(const ViewConst *__restrict__ views,
-                                                            const RenderConst *__restrict__ renders,
-                                                            const int *__restrict__ light_renders_off,
-                                                            const int *__restrict__ light_renders,
-                                                            const float *__restrict__ part_gm,
-                                                            const float *__restrict__ part_light,
-                                                            const float *__restrict__ part_render,
-                                                            float *__restrict__ gparams) {
-    const int l = blockIdx.x;
+// tiles, and the tiles of each render that uses it), in two passes so that a
+// few lights with many partials still fill the GPU: kGlightBlocks workgroups
+// per light each sum a strided share, then one thread per light adds their
+// results in a fixed order (deterministic, no atomics).
+__global__ __launch_bounds__(256) void glight_partial_kernel(const ViewConst *__restrict__ views,
+                                                             const RenderConst *__restrict__ renders,
+                                                             const int *__restrict__ light_renders_off,
+                                                             const int *__restrict__ light_renders,
+                                                             const float *__restrict__ part_gm,
+                                                             const float *__restrict__ part_light,
+                                                             const float *__restrict__ part_render,
+                                                             float *__restrict__ gl_part) {
+    const int l = blockIdx.y;
     const ViewConst &v = views[l];
+    const int first = blockIdx.x * blockDim.x + threadIdx.x, step = kGlightBlocks * blockDim.x;
     float acc[3] = {0.f, 0.f, 0.f};
     const int nvb = (v.nverts + 255) / 256;
-    for (int q = threadIdx.x; q < nvb; q += blockDim.x)
+    for (int q = first; q < nvb; q += step)
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc[k] += part_gm[((long long)v.part_gm_off + q) * 3 + k];
     const int nlt = v.tiles_x * v.tiles_y;
-    for (int q = threadIdx.x; q < nlt; q += blockDim.x)
+    for (int q = first; q < nlt; q += step)
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc[k] += part_light[((long long)v.part_off + q) * 3 + k];
     for (int e = light_renders_off[l]; e < light_renders_off[l + 1]; ++e) {
@@ -1055,11 +1059,20 @@ __global__ __launch_bounds__(256) void glight_reduce_kernel(const ViewConst *__r
         const RenderConst &R = renders[r];
         const ViewConst &cv = views[R.camera_view];
         const int nct = cv.tiles_x * cv.tiles_y;
-        for (int q = threadIdx.x; q < nct; q += blockDim.x)
+        for (int q = first; q < nct; q += step)
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[k] += part_render[R.part_off + ((long long)slot * nct + q) * 3 + k];
     }
-    block_sum_store<4>(acc, gparams + 3 * l);
+    block_sum_store<4>(acc, gl_part + ((long long)l * kGlightBlocks + blockIdx.x) * 3);
+}
+
+__global__ void glight_final_kernel(const float *__restrict__ gl_part, int L, float *__restrict__ gparams) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * L) return;
+    const int l = t / 3, k = t % 3;
+    float a = 0.f;
+    for (int b = 0; b < kGlightBlocks; ++b) a += gl_part[((long long)l * kGlightBlocks + b) * 3 + k];
+    gparams[t] = a;
 }
 
 // ----------------------------------------------------------------------------- pose
@@ -1262,10 +1275,14 @@ hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *co
 
 hipError_t launch_glight_reduce(const ViewConst *views, int L, const RenderConst *renders,
                                 const int *light_renders_off, const int *light_renders, const float *part_gm,
-                                const float *part_light, const float *part_render, float *gparams, hipStream_t s) {
+                                const float *part_light, const float *part_render, float *gl_part, float *gparams,
+                                hipStream_t s) {
     if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(glight_reduce_kernel, dim3(L), dim3(256), 0, s, views, renders, light_renders_off,
-                       light_renders, part_gm, part_light, part_render, gparams);
+    hipLaunchKernelGGL(glight_partial_kernel, dim3(kGlightBlocks, L), dim3(256), 0, s, views, renders,
+                       light_renders_off, light_renders, part_gm, part_light, part_render, gl_part);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(glight_final_kernel, dim3((3 * L + 255) / 256), dim3(256), 0, s, gl_part, L, gparams);
     return hipGetLastError();
 }
 
