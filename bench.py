@@ -39,14 +39,14 @@ HBM_PEAK_GBS = 8000.0
 PMC_FETCH_SCALE = 131072.0 / 65548.0
 PMC_WRITE_SCALE = 131072.0 / 131072.0
 PMC_TRAFFIC = {
-    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65858.2, write_kib=131072.0,
-                   sources=('blur.hip', 'dsm_internal.h'), sha1='484224a809f695cf'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65699.8, write_kib=131072.0,
-                       sources=('blur.hip', 'dsm_internal.h'), sha1='484224a809f695cf'),
-    'lookup': dict(kernel='lookup_kernel', fetch_kib=158567.0, write_kib=65536.0,
-                   sources=('shade.hip', 'dsm_internal.h'), sha1='787df741a9b03072'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=120400.9, write_kib=93785.9,
-                       sources=('grad.hip', 'dsm_internal.h'), sha1='1af6714cf74602cd'),
+    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65872.7, write_kib=131072.0,
+                   sources=('blur.hip', 'dsm_internal.h'), sha1='201b06be56b6e9cc'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65698.6, write_kib=131072.0,
+                       sources=('blur.hip', 'dsm_internal.h'), sha1='201b06be56b6e9cc'),
+    'lookup': dict(kernel='lookup_kernel', fetch_kib=158567.1, write_kib=65536.0,
+                   sources=('shade.hip', 'dsm_internal.h'), sha1='535a57030614c1ba'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=120400.5, write_kib=93809.4,
+                       sources=('grad.hip', 'dsm_internal.h'), sha1='340858702a9a3726'),
 }
 
 
