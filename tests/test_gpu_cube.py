@@ -43,7 +43,7 @@ def check_forward(b, g, o):
     assert g['stats']['bad_indices'] == 0
 
 
-@pytest.mark.parametrize('res,k,filt', [(136, 5, 'box'), (100, 7, 'gaussian')])
+@pytest.mark.parametrize('res,k,filt', [(136, 5, 'box'), (100, 7, 'gaussian'), (37, 1, 'box'), (64, 9, 'gaussian')])
 def test_cube_forward_matches_oracle(res, k, filt):
     b = cube_batch(res, k, filt)
     check_forward(b, gpu_run(b), oracle_run(b))
@@ -73,8 +73,9 @@ def test_cube_backward_matches_oracle_loss_gradient():
     assert np.all(g['glight'][2] == 0.0)
 
 
-def test_cube_backward_random_upstream_without_light_smoothing():
-    b = cube_batch(120, 3, 'box', antialias=False)
+@pytest.mark.parametrize('res,k', [(120, 3), (48, 9)])
+def test_cube_backward_random_upstream_without_light_smoothing(res, k):
+    b = cube_batch(res, k, 'box', antialias=False)
     G = clear_only(b, oracle_run(b), random_grad(b, 11))
     g = gpu_run(b, grad_images=G)
     o = oracle_run(b, grad_images=G)
