@@ -374,9 +374,15 @@ def loss_and_state(b, verts, lp, targets):
     return P.mse(out['images'], targets), P.fingerprint(out)
 
 
-def test_finite_differences_of_loss_cfg0(monkeypatch):
+@pytest.mark.parametrize('variant', ['plain', 'warped_bleed'])
+def test_finite_differences_of_loss_cfg0(monkeypatch, variant):
+    """Central differences of the loss against autograd, for the plain maps
+    and for exponential maps with light-bleeding reduction."""
     monkeypatch.setattr(cameras, 'ROUND_TO_F32', False)
     b = small_cfg0()
+    if variant == 'warped_bleed':
+        b.lights[0].warp_exponent = 10.0
+        b.lights[0].bleed_reduction = 0.2
     targets = P.target_images(b)
     base, poses, lp, alb = P.scene_leaves(b)
     L, fp0 = loss_and_state(b, base[0], lp[0], targets)
