@@ -368,6 +368,7 @@ def render(batch, verts_list, light_params, albedo_list=None, opts=Options()):
                                 if L.bleed_reduction > 0 else None,
                                 bleed_on=(vis_raw >= L.bleed_reduction).detach().numpy()
                                 if L.bleed_reduction > 0 else None,
+                                cone_on=(cone > 0).detach().numpy() if margin is not None else None,
                                 cone_margin=None if margin is None else margin.numpy())
         img0 = torch.zeros(W * H, batch.channels, dtype=D)
         img0 = img0.index_put((torch.as_tensor(flat),), col)
@@ -431,7 +432,7 @@ def fingerprint(out):
         if p is not None:
             parts += [p[k].tobytes() for k in ('T', 'O', 'a', 'b')]
         for li, f in fl.items():
-            for k in ('inside', 'lit_side', 'branch', 'clamp', 'floor', 'bleed_on'):
+            for k in ('inside', 'lit_side', 'branch', 'clamp', 'floor', 'bleed_on', 'cone_on'):
                 if f.get(k) is not None:
                     parts.append(np.asarray(f[k]).tobytes())
     return parts

@@ -207,3 +207,53 @@ def test_cube_padding_samples_along_the_continued_plane(S, P):
         worst = max(worst, np.abs(got - want)[edge].max())
     # bilinear error of a function with |Hessian| ~ 1 over texels of 2/S: ~ (2/S)^2
     assert worst < 2.0 * (2.0 / S) ** 2, worst
+
+
+def test_cube_light_loss_gradient_matches_finite_differences(monkeypatch):
+    """Central differences of the loss of a cube-light render (light moved
+    as one: all six faces' parameters together; and occluder vertices)
+    against autograd, where no discrete decision changes."""
+    monkeypatch.setattr(cameras, 'ROUND_TO_F32', False)
+    b = sg.cube_light_scene(resolution=48, view=48)
+    targets = P.target_images(b)
+    base, poses, lp, alb = P.scene_leaves(b)
+
+    def run(verts, params):
+        out = P.render(b, [verts], params)
+        return P.mse(out['images'], targets), P.fingerprint(out)
+
+    L0, fp0 = run(base[0], lp)
+    L0.backward()
+    g_light = sum(q.grad.numpy() for q in lp)
+    g_vert = base[0].grad.numpy()
+    h = 1e-6
+    rng = np.random.default_rng(4)
+    occluder = np.arange(17 * 17, len(base[0]))        # the sphere vertices follow the 17 x 17 ground grid
+    verts_to_check = rng.choice(occluder, 8, replace=False)
+    params = [('light', None, c) for c in range(3)] + [('vert', int(v), c) for v in verts_to_check for c in range(3)]
+    checked = skipped = 0
+    errs = []
+    for kind, v, c in params:
+        vals, same = [], True
+        for s in (+1, -1):
+            vv = base[0].detach().clone()
+            ll = [q.detach().clone() for q in lp]
+            if kind == 'light':
+                for q in ll:
+                    q[c] += s * h
+            else:
+                vv[v, c] += s * h
+            with torch.no_grad():
+                Ls, fps = run(vv, ll)
+            same &= fps == fp0
+            vals.append(float(Ls))
+        if not same:
+            skipped += 1
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = g_light[c] if kind == 'light' else g_vert[v, c]
+        errs.append(abs(fd - an) / max(abs(an), 1e-4))
+        checked += 1
+    assert checked >= 20, (checked, skipped)
+    assert max(errs) < 1e-4, max(errs)
+    assert np.linalg.norm(g_light) > 1e-4
