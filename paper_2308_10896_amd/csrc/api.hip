@@ -115,6 +115,16 @@ __global__ void zero_kernel(unsigned *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// Filtered maps are stored (m1, m2) interleaved per texel, side S + 2P with
+// the face at offset P; the getter hands out the two planes of the face.
+__global__ void deinterleave_kernel(const float *src, int S, int sp, int P, float *out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S * S) return;
+    const long long q = 2 * ((long long)(t / S + P) * sp + (t % S + P));
+    out[t] = src[q];
+    out[(long long)S * S + t] = src[q + 1];
+}
+
 hipError_t zero_async(void *p, size_t bytes, hipStream_t s) {
     const size_t n = bytes / 4;
     if (n == 0) return hipSuccess;
@@ -879,19 +889,15 @@ extern "C" dsm_status dsm_get_light_maps(const dsm_plan *p, const void *saved, c
     const ViewConst &v = p->views_h[light];
     const size_t base = which == 0 ? p->sv_F0 : which == 1 ? p->sc_F1 : p->sv_M;
     const void *src = which == 1 ? scratch : saved;
-    if (which == 2 && v.fpad) {
-        // the face itself, without the texels copied from its neighbours
-        const size_t sp = (size_t)v.W + 2 * (size_t)v.fpad;
-        for (int c = 0; c < 2; ++c)
-            DSM_TRY(hipMemcpy2DAsync(out + (size_t)c * v.W * v.W, 4 * (size_t)v.W,
-                                     at<char>(src, base + 4 * ((size_t)v.fmap_off + c * sp * sp +
-                                                                (size_t)v.fpad * sp + v.fpad)),
-                                     4 * sp, 4 * (size_t)v.W, (size_t)v.W, hipMemcpyDeviceToDevice,
-                                     (hipStream_t)stream));
+    if (which == 2) {
+        // the face itself (without texels sampled from cube neighbours), as two planes
+        hipLaunchKernelGGL(deinterleave_kernel, dim3((v.W * v.W + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                           at<float>(src, base + 4 * (size_t)v.fmap_off), v.W, v.W + 2 * v.fpad, v.fpad, out);
+        DSM_TRY(hipGetLastError());
         return DSM_OK;
     }
-    DSM_TRY(hipMemcpyAsync(out, at<char>(src, base + 4 * (size_t)(which == 2 ? v.fmap_off : v.map_off)),
-                           8 * (size_t)v.W * v.W, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    DSM_TRY(hipMemcpyAsync(out, at<char>(src, base + 4 * (size_t)v.map_off), 8 * (size_t)v.W * v.W,
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return DSM_OK;
 }
 

@@ -55,7 +55,10 @@ struct BlurGeom {
 // jobs != nullptr: one flattened grid over the tiles of every job of this
 // radius.  jobs == nullptr: every map uses `single`, the grid holds per_map
 // tiles of each map in turn, and map m sits 2*S*S*m floats after the first.
-template <bool ADJ, int R>
+// IL: the filtered side (the output of the forward pass, the input of the
+// transpose) holds (m1, m2) interleaved per texel, so that a bilinear tap of
+// the lookup is one 8-byte load; the smoothed side stays channel-planar.
+template <bool ADJ, int R, bool IL>
 __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__restrict__ jobs, int njobs,
                                                             BlurJob single, int per_map,
                                                             const float *__restrict__ in, float *__restrict__ out) {
@@ -85,7 +88,53 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
         return (size_t)(ok ? gy : 0) * S;
     };
     const bool vec = (S & 3) == 0 && x0 + kBlurTX <= S && ((J.in_off | J.out_off) & 3) == 0;
-    {
+    // interleaved input texel (channel ch) of map row offset ro, column gx
+    auto iload = [&](int ch, size_t ro, int gx) { return src[2 * (ro + gx) + ch]; };
+    if (IL && ADJ) {
+        // two 16-byte loads hold four texels of both channels
+#pragma unroll
+        for (int i = 0; i < (G::NQ + kBlurThreads - 1) / kBlurThreads; ++i) {
+            const int r = tid + i * kBlurThreads;
+            if (r < G::NQ) {
+                const int l = r >> 4, cq = r & 15;
+                bool rok;
+                const size_t ro = row_of(l, rok);
+                float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (vec) {
+                    if (rok) {
+                        const float4 lo = *(const float4 *)(src + 2 * (ro + x0 + 4 * cq));
+                        const float4 hi = *(const float4 *)(src + 2 * (ro + x0 + 4 * cq) + 4);
+                        a[0] = lo.x; a[1] = lo.y; a[2] = lo.z; a[3] = lo.w;
+                        a[4] = hi.x; a[5] = hi.y; a[6] = hi.z; a[7] = hi.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int gx = x0 + 4 * cq + e;
+                        if (rok && gx < S) {
+                            a[2 * e] = iload(0, ro, gx);
+                            a[2 * e + 1] = iload(1, ro, gx);
+                        }
+                    }
+                }
+                *(float4 *)&tile_s[0][l][H4 + 4 * cq] = make_float4(a[0], a[2], a[4], a[6]);
+                *(float4 *)&tile_s[1][l][H4 + 4 * cq] = make_float4(a[1], a[3], a[5], a[7]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G::HPT; ++i) {
+            const int slot = tid + i * kBlurThreads;
+            if (R > 0 && slot < 2 * G::NH) {
+                const int ch = slot >= G::NH, r = slot - ch * G::NH;
+                const int l = r / (2 * R), e = r - l * (2 * R);
+                const int gx = e < R ? x0 - R + e : x0 + kBlurTX + (e - R);
+                bool ok;
+                const size_t ro = row_of(l, ok);
+                ok = ok && gx >= 0 && gx < S;
+                tile_s[ch][l][e < R ? H4 - R + e : H4 + kBlurTX + (e - R)] = ok ? iload(ch, ro, gx) : 0.f;
+            }
+        }
+    } else {
         float4 q[G::QPT];
         float h[G::HPT];
         if (vec) {
@@ -232,8 +281,12 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
         }
         if (yy < S && x < S) {
             const size_t o = (size_t)yy * S + x;
-            dst[o] = va;
-            dst[plane + o] = vb;
+            if (IL && !ADJ) {
+                *(float2 *)(dst + 2 * o) = make_float2(va, vb);
+            } else {
+                dst[o] = va;
+                dst[plane + o] = vb;
+            }
         }
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) {
@@ -246,13 +299,13 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
     }
 }
 
-template <bool ADJ>
+template <bool ADJ, bool IL>
 static hipError_t launch_r(int R, dim3 grid, const BlurJob *jobs, int njobs, const BlurJob &single, int per_map,
                            const float *in, float *out, hipStream_t s) {
-#define DSM_BR(RR)                                                                                                \
-    case RR:                                                                                                     \
-        hipLaunchKernelGGL((blur_kernel<ADJ, RR>), grid, dim3(kBlurThreads), 0, s, jobs, njobs, single, per_map, \
-                           in, out);                                                                              \
+#define DSM_BR(RR)                                                                                                    \
+    case RR:                                                                                                         \
+        hipLaunchKernelGGL((blur_kernel<ADJ, RR, IL>), grid, dim3(kBlurThreads), 0, s, jobs, njobs, single, per_map, \
+                           in, out);                                                                                  \
         break;
     switch (R) {
         DSM_BR(0) DSM_BR(1) DSM_BR(2) DSM_BR(3) DSM_BR(4) DSM_BR(5) DSM_BR(6) DSM_BR(7)
@@ -272,8 +325,8 @@ hipError_t launch_blur(const BlurJob *jobs_dev, int njobs, int total_tiles, cons
                        bool adjoint, int R, hipStream_t s) {
     if (total_tiles == 0 || njobs == 0) return hipSuccess;
     BlurJob none{};
-    if (adjoint) return launch_r<true>(R, dim3(total_tiles), jobs_dev, njobs, none, 1, in, out, s);
-    return launch_r<false>(R, dim3(total_tiles), jobs_dev, njobs, none, 1, in, out, s);
+    if (adjoint) return launch_r<true, true>(R, dim3(total_tiles), jobs_dev, njobs, none, 1, in, out, s);
+    return launch_r<false, true>(R, dim3(total_tiles), jobs_dev, njobs, none, 1, in, out, s);
 }
 
 hipError_t launch_blur_uniform(const BlurJob &job, int n_maps, const float *in, float *out, bool adjoint,
@@ -286,8 +339,8 @@ hipError_t launch_blur_uniform(const BlurJob &job, int n_maps, const float *in, 
     const long long total = (long long)per_map * n_maps;
     if (total >= (1LL << 31)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)total);
-    if (adjoint) return launch_r<true>(R, grid, nullptr, 0, j, per_map, in, out, s);
-    return launch_r<false>(R, grid, nullptr, 0, j, per_map, in, out, s);
+    if (adjoint) return launch_r<true, false>(R, grid, nullptr, 0, j, per_map, in, out, s);
+    return launch_r<false, false>(R, grid, nullptr, 0, j, per_map, in, out, s);
 }
 
 void filter_taps_host(int filter, int k, float sigma, float *w) {

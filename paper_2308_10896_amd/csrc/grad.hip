@@ -423,7 +423,9 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         // filtered maps are stored with side Sp; cube faces keep P texels of
         // their neighbours around the face, so taps may cross the seam
         const int P = l.fpad, Sp = S + 2 * P;
-        const float *ma = maps + l.fmap_off, *mb = maps + l.fmap_off + (long long)Sp * Sp;
+        // filtered maps hold (m1, m2) interleaved per texel
+        const float2 *mm = (const float2 *)(maps + l.fmap_off);
+        float2 t00 = make_float2(0.f, 0.f), t01 = t00, t10 = t00, t11 = t00;
         if (inside) {
             const float sx = (ux + 1.f) * (0.5f * S) - 0.5f;
             const float sy = (1.f - uy) * (0.5f * S) - 0.5f;
@@ -438,8 +440,9 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
             o00 = (long long)y0 * Sp + x0; o01 = (long long)y0 * Sp + x1;
             o10 = (long long)y1 * Sp + x0; o11 = (long long)y1 * Sp + x1;
-            m1 = ((w00 * ma[o00] + w01 * ma[o01]) + w10 * ma[o10]) + w11 * ma[o11];
-            m2 = ((w00 * mb[o00] + w01 * mb[o01]) + w10 * mb[o10]) + w11 * mb[o11];
+            t00 = mm[o00]; t01 = mm[o01]; t10 = mm[o10]; t11 = mm[o11];
+            m1 = ((w00 * t00.x + w01 * t01.x) + w10 * t10.x) + w11 * t11.x;
+            m2 = ((w00 * t00.y + w01 * t01.y) + w10 * t10.y) + w11 * t11.y;
             float depth;
             if (l.kind == kDirectional)
                 depth = ((x - l.pos[0]) * l.dir[0] + (y - l.pos[1]) * l.dir[1]) + (z - l.pos[2]) * l.dir[2];
@@ -530,7 +533,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             }
             // bilinear scatter to the moment maps
             if (DIRECT) {
-                float *ga = gmaps + l.fmap_off, *gb = gmaps + l.fmap_off + (long long)Sp * Sp;
+                float *ga = gmaps + l.fmap_off, *gb = gmaps + l.fmap_off + 1;      // interleaved: texel o at 2 o
+                o00 *= 2; o01 *= 2; o10 *= 2; o11 *= 2;
                 const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
                 atomic_add_f32(ga + o00, gm1 * w00); atomic_add_f32(ga + o01, gm1 * w01);
                 atomic_add_f32(ga + o10, gm1 * w10); atomic_add_f32(ga + o11, gm1 * w11);
@@ -540,10 +544,10 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                 hits[q] = MapHit{ixs, iys, fx, fy, gm1, gm2};
             }
             // the map position moves with x and with the light camera
-            const float dm1fx = (1.f - fy) * (ma[o01] - ma[o00]) + fy * (ma[o11] - ma[o10]);
-            const float dm1fy = (1.f - fx) * (ma[o10] - ma[o00]) + fx * (ma[o11] - ma[o01]);
-            const float dm2fx = (1.f - fy) * (mb[o01] - mb[o00]) + fy * (mb[o11] - mb[o10]);
-            const float dm2fy = (1.f - fx) * (mb[o10] - mb[o00]) + fx * (mb[o11] - mb[o01]);
+            const float dm1fx = (1.f - fy) * (t01.x - t00.x) + fy * (t11.x - t10.x);
+            const float dm1fy = (1.f - fx) * (t10.x - t00.x) + fx * (t11.x - t01.x);
+            const float dm2fx = (1.f - fy) * (t01.y - t00.y) + fy * (t11.y - t10.y);
+            const float dm2fy = (1.f - fx) * (t10.y - t00.y) + fx * (t11.y - t01.y);
             const float gsx = gm1 * dm1fx + gm2 * dm2fx;
             const float gsy = gm1 * dm1fy + gm2 * dm2fy;
             const float hs = 0.5f * S;
@@ -612,7 +616,6 @@ __device__ __forceinline__ void map_window_scatter(const MapHit (&hit)[PPT], int
     const bool any = mx != 0x7fffffff;
     for (int e = lane; e < 2 * WIN * WIN; e += 64) (&win[w][0][0])[e] = 0.f;
     __syncthreads();
-    const long long plane = (long long)S * S;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const MapHit &h = hit[k];
@@ -630,9 +633,9 @@ __device__ __forceinline__ void map_window_scatter(const MapHit (&hit)[PPT], int
             atomicAdd(b + o00, h.gm2 * w00); atomicAdd(b + o01, h.gm2 * w01);
             atomicAdd(b + o10, h.gm2 * w10); atomicAdd(b + o11, h.gm2 * w11);
         } else {
-            float *a = gmap, *b = gmap + plane;
-            const long long o00 = (long long)y0 * S + x0, o01 = (long long)y0 * S + x1;
-            const long long o10 = (long long)y1 * S + x0, o11 = (long long)y1 * S + x1;
+            float *a = gmap, *b = gmap + 1;          // interleaved (m1, m2): texel o at 2 o
+            const long long o00 = 2 * ((long long)y0 * S + x0), o01 = 2 * ((long long)y0 * S + x1);
+            const long long o10 = 2 * ((long long)y1 * S + x0), o11 = 2 * ((long long)y1 * S + x1);
             atomic_add_f32(a + o00, h.gm1 * w00); atomic_add_f32(a + o01, h.gm1 * w01);
             atomic_add_f32(a + o10, h.gm1 * w10); atomic_add_f32(a + o11, h.gm1 * w11);
             atomic_add_f32(b + o00, h.gm2 * w00); atomic_add_f32(b + o01, h.gm2 * w01);
@@ -644,9 +647,9 @@ __device__ __forceinline__ void map_window_scatter(const MapHit (&hit)[PPT], int
         for (int e = lane; e < WIN * WIN; e += 64) {
             const int gx = mx + e % WIN, gy = my + e / WIN;
             if (gx >= S || gy >= S) continue;
-            const long long o = (long long)gy * S + gx;
+            const long long o = 2 * ((long long)gy * S + gx);
             atomic_add_f32(gmap + o, win[w][0][e]);
-            atomic_add_f32(gmap + plane + o, win[w][1][e]);
+            atomic_add_f32(gmap + o + 1, win[w][1][e]);
         }
     __syncthreads();
 }

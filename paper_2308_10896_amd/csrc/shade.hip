@@ -163,13 +163,14 @@ __device__ __forceinline__ Fetch bilinear2(const float *__restrict__ maps, long 
     f.x1 = min(max(ix + 1, 0), S - 1);
     f.y0 = min(max(iy, 0), S - 1);
     f.y1 = min(max(iy + 1, 0), S - 1);
-    const float *a = maps + off, *b = maps + off + (long long)S * S;
+    const float2 *m = (const float2 *)(maps + off);          // (m1, m2) interleaved per texel
     const long long o00 = (long long)f.y0 * S + f.x0, o01 = (long long)f.y0 * S + f.x1;
     const long long o10 = (long long)f.y1 * S + f.x0, o11 = (long long)f.y1 * S + f.x1;
     const float w00 = (1.f - f.fx) * (1.f - f.fy), w01 = f.fx * (1.f - f.fy);
     const float w10 = (1.f - f.fx) * f.fy, w11 = f.fx * f.fy;
-    f.m1 = ((w00 * a[o00] + w01 * a[o01]) + w10 * a[o10]) + w11 * a[o11];
-    f.m2 = ((w00 * b[o00] + w01 * b[o01]) + w10 * b[o10]) + w11 * b[o11];
+    const float2 t00 = m[o00], t01 = m[o01], t10 = m[o10], t11 = m[o11];
+    f.m1 = ((w00 * t00.x + w01 * t01.x) + w10 * t10.x) + w11 * t11.x;
+    f.m2 = ((w00 * t00.y + w01 * t01.y) + w10 * t10.y) + w11 * t11.y;
     return f;
 }
 
