@@ -39,14 +39,14 @@ HBM_PEAK_GBS = 8000.0
 PMC_FETCH_SCALE = 131072.0 / 65548.0
 PMC_WRITE_SCALE = 131072.0 / 131072.0
 PMC_TRAFFIC = {
-    'filter': dict(kernel='blur_kernel<false, 2>', fetch_kib=65872.7, write_kib=131072.0,
-                   sources=('blur.hip', 'dsm_internal.h'), sha1='201b06be56b6e9cc'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2>', fetch_kib=65698.6, write_kib=131072.0,
-                       sources=('blur.hip', 'dsm_internal.h'), sha1='201b06be56b6e9cc'),
-    'lookup': dict(kernel='lookup_kernel', fetch_kib=158567.1, write_kib=65536.0,
-                   sources=('shade.hip', 'dsm_internal.h'), sha1='535a57030614c1ba'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=120400.5, write_kib=93809.4,
-                       sources=('grad.hip', 'dsm_internal.h'), sha1='340858702a9a3726'),
+    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=66020.0, write_kib=131072.0,
+                   sources=('blur.hip', 'dsm_internal.h'), sha1='05cf1f9247186497'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65837.7, write_kib=131072.0,
+                       sources=('blur.hip', 'dsm_internal.h'), sha1='05cf1f9247186497'),
+    'lookup': dict(kernel='lookup_kernel', fetch_kib=150556.1, write_kib=65536.0,
+                   sources=('shade.hip', 'dsm_internal.h'), sha1='2feaf5e1a02511a1'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=118256.0, write_kib=100924.7,
+                       sources=('grad.hip', 'dsm_internal.h'), sha1='17d7aa23a0531633'),
 }
 
 
@@ -233,8 +233,10 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
 
     * every stage of forward + backward, eager, via the library's stage
       timer (each targeted stage is one kernel launch);
-    * the moment filter forward / transpose again as back-to-back launches of
-      the same kernel on the batch's own smoothed maps;
+    * the moment filter forward / transpose again as back-to-back launches
+      of the stand-alone filter (the same kernel with both sides
+      channel-planar; in the pipeline the filtered side is interleaved) on
+      the batch's own smoothed maps;
     * a plain device-to-device copy of the same size, for the achievable
       bandwidth on this GPU.
 
