@@ -91,23 +91,27 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
     // interleaved input texel (channel ch) of map row offset ro, column gx
     auto iload = [&](int ch, size_t ro, int gx) { return src[2 * (ro + gx) + ch]; };
     if (IL && ADJ) {
-        // two 16-byte loads hold four texels of both channels
+        // two 16-byte loads hold four texels of both channels; every load is
+        // issued before the first LDS store, as in the planar path
+        constexpr int NI = (G::NQ + kBlurThreads - 1) / kBlurThreads;
+        float4 lo[NI], hi[NI];
+        float h[G::HPT];
 #pragma unroll
-        for (int i = 0; i < (G::NQ + kBlurThreads - 1) / kBlurThreads; ++i) {
+        for (int i = 0; i < NI; ++i) {
             const int r = tid + i * kBlurThreads;
+            lo[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            hi[i] = lo[i];
             if (r < G::NQ) {
                 const int l = r >> 4, cq = r & 15;
                 bool rok;
                 const size_t ro = row_of(l, rok);
-                float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 if (vec) {
                     if (rok) {
-                        const float4 lo = *(const float4 *)(src + 2 * (ro + x0 + 4 * cq));
-                        const float4 hi = *(const float4 *)(src + 2 * (ro + x0 + 4 * cq) + 4);
-                        a[0] = lo.x; a[1] = lo.y; a[2] = lo.z; a[3] = lo.w;
-                        a[4] = hi.x; a[5] = hi.y; a[6] = hi.z; a[7] = hi.w;
+                        lo[i] = *(const float4 *)(src + 2 * (ro + x0 + 4 * cq));
+                        hi[i] = *(const float4 *)(src + 2 * (ro + x0 + 4 * cq) + 4);
                     }
                 } else {
+                    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int gx = x0 + 4 * cq + e;
@@ -116,9 +120,31 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
                             a[2 * e + 1] = iload(1, ro, gx);
                         }
                     }
+                    lo[i] = make_float4(a[0], a[1], a[2], a[3]);
+                    hi[i] = make_float4(a[4], a[5], a[6], a[7]);
                 }
-                *(float4 *)&tile_s[0][l][H4 + 4 * cq] = make_float4(a[0], a[2], a[4], a[6]);
-                *(float4 *)&tile_s[1][l][H4 + 4 * cq] = make_float4(a[1], a[3], a[5], a[7]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G::HPT; ++i) {
+            const int slot = tid + i * kBlurThreads;
+            h[i] = 0.f;
+            if (R > 0 && slot < 2 * G::NH) {
+                const int ch = slot >= G::NH, r = slot - ch * G::NH;
+                const int l = r / (2 * R), e = r - l * (2 * R);
+                const int gx = e < R ? x0 - R + e : x0 + kBlurTX + (e - R);
+                bool ok;
+                const size_t ro = row_of(l, ok);
+                if (ok && gx >= 0 && gx < S) h[i] = iload(ch, ro, gx);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int r = tid + i * kBlurThreads;
+            if (r < G::NQ) {
+                const int l = r >> 4, cq = r & 15;
+                *(float4 *)&tile_s[0][l][H4 + 4 * cq] = make_float4(lo[i].x, lo[i].z, hi[i].x, hi[i].z);
+                *(float4 *)&tile_s[1][l][H4 + 4 * cq] = make_float4(lo[i].y, lo[i].w, hi[i].y, hi[i].w);
             }
         }
 #pragma unroll
@@ -127,11 +153,7 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
             if (R > 0 && slot < 2 * G::NH) {
                 const int ch = slot >= G::NH, r = slot - ch * G::NH;
                 const int l = r / (2 * R), e = r - l * (2 * R);
-                const int gx = e < R ? x0 - R + e : x0 + kBlurTX + (e - R);
-                bool ok;
-                const size_t ro = row_of(l, ok);
-                ok = ok && gx >= 0 && gx < S;
-                tile_s[ch][l][e < R ? H4 - R + e : H4 + kBlurTX + (e - R)] = ok ? iload(ch, ro, gx) : 0.f;
+                tile_s[ch][l][e < R ? H4 - R + e : H4 + kBlurTX + (e - R)] = h[i];
             }
         }
     } else {
