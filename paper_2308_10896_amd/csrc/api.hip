@@ -647,8 +647,8 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
-    DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts, tv,
-                             s));
+    DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts,
+                             albedo, p->C, tv, s));
     signed char *facing8 = at<signed char>(scratch, p->sc_facing);
     DSM_TRY(launch_setup(p->views_d, p->nviews, p->max_faces, p->faces_d, clip, setup, facing8, pair_cnt, p->tile,
                          cnt, s));

@@ -248,7 +248,7 @@ __device__ __forceinline__ float4 clip_of(const float *M, float x, float y, floa
 // World positions of a triangle's three corners, packed as three float4
 // (x0 y0 z0 x1 | y1 z1 x2 y2 | z2 - - -), one record per face of the batch.
 struct TriVerts {
-    float4 a, b, c;
+    float4 a, b, c;     // x0 y0 z0 x1 | y1 z1 x2 y2 | z2 albedo[0..2]
 };
 
 __device__ __forceinline__ void atomic_add_f32(float *p, float v) {
@@ -303,7 +303,8 @@ hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int
                          const int *render_lights, const TriVerts *tv, const float *albedo,
                          const unsigned long long *keys, const float *maps, float *img0, int C, hipStream_t s);
 hipError_t launch_tri_verts(const int *scene_vert_off, const int *scene_face_off, int B, int max_faces,
-                            const int *faces, const float *verts, TriVerts *tv, hipStream_t s);
+                            const int *faces, const float *verts, const float *albedo, int C, TriVerts *tv,
+                            hipStream_t s);
 // backward
 hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
                                      const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,

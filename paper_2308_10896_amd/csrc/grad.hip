@@ -395,7 +395,7 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
     const float rn0 = __builtin_amdgcn_rcpf(nn);
     const float nx = crx * rn0, ny = cry * rn0, nz = crz * rn0;
     float rho[3] = {0.f, 0.f, 0.f};
-    for (int c = 0; c < C; ++c) rho[c] = albedo[(size_t)(cv.face_off + tri) * C + c];
+    for (int c = 0; c < C; ++c) rho[c] = c == 0 ? r.c.y : c == 1 ? r.c.z : r.c.w;   // from the face record
     float srho = 0.f;
     for (int c = 0; c < C; ++c) srho += g[c] * rho[c];
     float gx[3] = {0, 0, 0}, gn[3] = {0, 0, 0};

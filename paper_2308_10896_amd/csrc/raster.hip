@@ -81,7 +81,7 @@ __global__ void transform_kernel(const ViewConst *__restrict__ views, const floa
 // so that per-pixel passes fetch one record instead of face -> vertices.
 __global__ void tri_verts_kernel(const int *__restrict__ scene_vert_off, const int *__restrict__ scene_face_off,
                                  const int *__restrict__ faces, const float *__restrict__ verts,
-                                 TriVerts *__restrict__ tv) {
+                                 const float *__restrict__ albedo, int C, TriVerts *__restrict__ tv) {
     const int b = blockIdx.y;
     const int f = scene_face_off[b] + blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= scene_face_off[b + 1]) return;
@@ -91,15 +91,19 @@ __global__ void tri_verts_kernel(const int *__restrict__ scene_vert_off, const i
     TriVerts r;
     r.a = make_float4(v0[0], v0[1], v0[2], v1[0]);
     r.b = make_float4(v1[1], v1[2], v2[0], v2[1]);
-    r.c = make_float4(v2[2], 0.f, 0.f, 0.f);
+    // the face's albedo rides in the record's spare words: the lookups read it
+    // with the corners instead of with a load of its own
+    const float *rho = albedo + (size_t)f * C;
+    r.c = make_float4(v2[2], rho[0], C > 1 ? rho[1] : 0.f, C > 2 ? rho[2] : 0.f);
     tv[f] = r;
 }
 
 hipError_t launch_tri_verts(const int *scene_vert_off, const int *scene_face_off, int B, int max_faces,
-                            const int *faces, const float *verts, TriVerts *tv, hipStream_t s) {
+                            const int *faces, const float *verts, const float *albedo, int C, TriVerts *tv,
+                            hipStream_t s) {
     if (B == 0 || max_faces == 0) return hipSuccess;
     hipLaunchKernelGGL(tri_verts_kernel, dim3((max_faces + 255) / 256, B), dim3(256), 0, s, scene_vert_off,
-                       scene_face_off, faces, verts, tv);
+                       scene_face_off, faces, verts, albedo, C, tv);
     return hipGetLastError();
 }
 

@@ -254,7 +254,7 @@ __global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderC
         }
         shade += lam * vis * l.intensity * cone;
     }
-    const float *rho = albedo + (size_t)(cv.face_off + tri) * C;
+    const float rho[3] = {r.c.y, r.c.z, r.c.w};          // albedo, carried in the face record
     for (int c = 0; c < C; ++c) out[c] = rho[c] * shade;
 }
 
