@@ -39,14 +39,14 @@ HBM_PEAK_GBS = 8000.0
 PMC_FETCH_SCALE = 131072.0 / 65548.0
 PMC_WRITE_SCALE = 131072.0 / 131072.0
 PMC_TRAFFIC = {
-    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=66044.2, write_kib=131072.0,
-                   sources=('blur.hip', 'dsm_internal.h'), sha1='fb1912cf3bc2e826'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65734.4, write_kib=131072.0,
-                       sources=('blur.hip', 'dsm_internal.h'), sha1='fb1912cf3bc2e826'),
-    'lookup': dict(kernel='lookup_kernel', fetch_kib=150556.2, write_kib=65536.0,
-                   sources=('shade.hip', 'dsm_internal.h'), sha1='2feaf5e1a02511a1'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=118255.7, write_kib=100938.8,
-                       sources=('grad.hip', 'dsm_internal.h'), sha1='17d7aa23a0531633'),
+    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=66045.6, write_kib=131072.0,
+                   sources=('blur.hip', 'dsm_internal.h'), sha1='539cac5eb6138bfe'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65732.1, write_kib=131072.0,
+                       sources=('blur.hip', 'dsm_internal.h'), sha1='539cac5eb6138bfe'),
+    'lookup': dict(kernel='lookup_kernel', fetch_kib=147629.7, write_kib=65536.0,
+                   sources=('shade.hip', 'dsm_internal.h'), sha1='eb1fd9388ed8d3d8'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=117630.8, write_kib=100958.9,
+                       sources=('grad.hip', 'dsm_internal.h'), sha1='dbeeadd925665920'),
 }
 
 
