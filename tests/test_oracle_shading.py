@@ -211,6 +211,33 @@ def test_edge_smoothing_row_sum_equals_covered_length():
         assert abs(out[j].sum() - (cf * e + cb * (W - e))) < 1e-12
 
 
+def test_edge_smoothing_column_sum_equals_covered_length():
+    """One near-horizontal silhouette edge over a constant background, the
+    vertical-pair half of the smoothing: after smoothing, every column sums
+    to c_f * e + c_b * (H - e), e the continuous crossing of the edge with
+    that column's sample line (measured from the top of the screen)."""
+    W, H = 26, 22
+    left = (-1.6, 0.17)     # NDC (x, y), edge leaves the screen left and right
+    right = (1.6, -0.23)
+    verts = np.array([[-1.6, 1.6], [1.6, 1.6], list(right), list(left)], np.float32)
+    clip32 = np.concatenate([verts, np.zeros((4, 1), np.float32), np.ones((4, 1), np.float32)], 1)
+    faces = np.array([[0, 3, 2], [0, 2, 1]])
+    st = raster.setup(clip32, faces, W, H)
+    key, tri = raster.coverage(st)
+    pairs = raster.aa_pairs(key, tri, st, Adjacency(faces))
+    assert len(pairs['T']) > 0 and not pairs['horiz'].any()
+    cf, cb = 0.9, 0.2
+    img = torch.as_tensor(np.where(tri.ravel() >= 0, cf, cb)[:, None])
+    out = P.smooth_edges(img, pairs, torch.as_tensor(clip32, dtype=D), W, H).reshape(H, W).numpy()
+    l64, r64 = verts[3].astype(np.float64), verts[2].astype(np.float64)
+    lx, rx = (l64[0] + 1) * W / 2, (r64[0] + 1) * W / 2
+    ly, ry = (1 - l64[1]) * H / 2, (1 - r64[1]) * H / 2
+    for i in range(W):
+        x = i + 0.5
+        e = ly + (ry - ly) * (x - lx) / (rx - lx)
+        assert abs(out[:, i].sum() - (cf * e + cb * (H - e))) < 1e-12
+
+
 def test_no_silhouette_means_identity():
     W = H = 20
     quad = np.array([[-1, 1], [1, 1], [1, -1], [-1, -1]], np.float32)
@@ -291,6 +318,54 @@ def test_no_occluder_means_fully_lit():
     w = b.lights[0].param.astype(np.float64)
     w /= np.linalg.norm(w)
     assert np.all(img0 >= 0.8 * (-w[1]) * (1 - 1e-6))
+
+
+def test_spot_cone_is_hard_half_angle_mask():
+    """Spot light (Sec. 5 light types; the supplementary renderer uses a
+    perspective light camera whose field of view is the cone): on an
+    unoccluded ground plane under a spot with a 60 degree cone, a pixel
+    whose direction from the light makes more than 30 degrees with the cone
+    axis is exactly 0, and one well inside the cone is exactly
+    rho max(0, n . omega).  The world point of each pixel is found here by
+    intersecting the camera ray with the plane, independently of the
+    oracle's projection and barycentrics; the angle is taken from the
+    light's position and aim point as given in the scene."""
+    qv, qf = sg.quad(4.0)
+    sc = sg.Scene(verts=qv, faces=qf, albedo=np.full((2, 1), 0.8, np.float32))
+    p = sg.f32([1, 5, 1])
+    L = sg.Light('spot', p, fov_deg=60.0, resolution=128, filter='gaussian', k=7, sigma=2.0,
+                 up=sg._up_for(-p))
+    cam = sg.Camera(eye=sg.f32([0, 3, 5]), target=sg.f32([0, 0.75, 0]), fov_deg=45.0, width=128, height=112)
+    b = sg.Batch('spot', [sc], [L], [cam], [sg.Render(0, [0])])
+    base, poses, lp, alb = P.scene_leaves(b, requires_grad=False)
+    img = P.render(b, P.world_vertices(b, base, poses), lp, alb)['images'][0][..., 0].numpy()
+    W, H = cam.width, cam.height
+    e = cam.eye.astype(np.float64)
+    f = cam.target.astype(np.float64) - e
+    f /= np.linalg.norm(f)
+    s = np.cross(f, [0.0, 1.0, 0.0])
+    s /= np.linalg.norm(s)
+    u = np.cross(s, f)
+    th = math.tan(math.radians(cam.fov_deg) / 2)
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing='ij')
+    px = 2 * (ii + 0.5) / W - 1
+    py = 1 - 2 * (jj + 0.5) / H
+    ray = f + (px * th * W / H)[..., None] * s + (py * th)[..., None] * u
+    t = -e[1] / ray[..., 1]
+    x = e + t[..., None] * ray
+    pl = p.astype(np.float64)
+    v = x - pl
+    axis = (L.target.astype(np.float64) - pl) / np.linalg.norm(L.target.astype(np.float64) - pl)
+    ang = np.degrees(np.arccos((v @ axis) / np.linalg.norm(v, axis=-1)))
+    lam = 0.8 * (-v[..., 1] / np.linalg.norm(v, axis=-1))      # n = +y, omega toward the light
+    on_plane = (t > 0) & (np.abs(x[..., 0]) < 3.9) & (np.abs(x[..., 2]) < 3.9)
+    outside = on_plane & (ang > 30.05)
+    inside = on_plane & (ang < 28.0)      # 2 degrees: the filter's reach near the map border
+    rim = on_plane & (ang > 29.5) & (ang < 29.95)
+    assert outside.sum() > 500 and inside.sum() > 5000 and rim.sum() > 40
+    assert np.all(img[outside] == 0.0)
+    assert np.abs(img[inside] - lam[inside]).max() < 1e-6
+    assert np.all(img[rim] > 0.5 * lam[rim])
 
 
 def hard_shadow_batch(cfg):
@@ -415,8 +490,60 @@ def test_finite_differences_of_loss_cfg0(monkeypatch, variant):
         errs.append(abs(fd - an) / max(abs(an), 1e-4))
         checked += 1
     assert checked >= 25, (checked, skipped)
-    assert max(errs) < 1e-4, max(errs)
+    # float64 central differences with h = 1e-6 resolve the derivative to
+    # about 1e-9 relative here (warped maps: the exponentials' larger
+    # curvature leaves about 1e-6)
+    tol = 1e-6 if variant == 'plain' else 5e-6
+    assert max(errs) < tol, max(errs)
     assert np.linalg.norm(gl) > 1e-4
+
+
+def test_finite_differences_of_loss_cfg1_sphere_vertices(monkeypatch):
+    """Central differences on the icosphere under the spot light (Gaussian 7):
+    32 sphere vertices drawn with default_rng(1), each moved along a seeded
+    random unit direction, and the three light coordinates.  A sample counts
+    only where every discrete decision is unchanged at both offsets."""
+    monkeypatch.setattr(cameras, 'ROUND_TO_F32', False)
+    b = sg.config1()
+    b.lights[0].resolution = 96
+    b.cameras[0].width = b.cameras[0].height = 96
+    n_sphere = len(b.scenes[0].verts) - 4
+    chosen = np.random.default_rng(1).choice(n_sphere, 32, replace=False)
+    dirs = np.random.default_rng(2).standard_normal((32, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    targets = P.target_images(b)
+    base, poses, lp, alb = P.scene_leaves(b)
+    L, fp0 = loss_and_state(b, base[0], lp[0], targets)
+    L.backward()
+    gv = base[0].grad.numpy()
+    gl = lp[0].grad.numpy()
+    h = 1e-6
+    probes = [('light', np.eye(3)[c], gl[c]) for c in range(3)]
+    probes += [(int(v), d, float(gv[v] @ d)) for v, d in zip(chosen, dirs)]
+    errs, skipped, nonzero = [], 0, 0
+    for what, d, an in probes:
+        vals = []
+        same = True
+        for sgn in (+1, -1):
+            vv = base[0].detach().clone()
+            ll = lp[0].detach().clone()
+            if what == 'light':
+                ll += sgn * h * torch.as_tensor(d)
+            else:
+                vv[what] += sgn * h * torch.as_tensor(d)
+            with torch.no_grad():
+                Ls, fps = loss_and_state(b, vv, ll, targets)
+            same &= fps == fp0
+            vals.append(float(Ls))
+        if not same:
+            skipped += 1
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        nonzero += abs(an) > 1e-6
+        errs.append(abs(fd - an) / max(abs(an), 1e-4))
+    print(f"checked {len(errs)}, skipped {skipped}, nonzero {nonzero}, worst {max(errs):.2e}")
+    assert len(errs) >= 28 and nonzero >= 8, (len(errs), skipped, nonzero)
+    assert max(errs) < 1e-6, max(errs)
 
 
 def test_gradient_step_on_light_lowers_loss():
