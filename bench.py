@@ -147,7 +147,7 @@ def main():
     t_batched = timed(step_batched, args.steps, stream)
     R = len(batch.renders)
     batched_rps = R * args.steps / t_batched
-    st = plan.stats(scratch)
+    st = plan.stats(saved)
     assert st['culled'] == 0 and st['bad_indices'] == 0, st
 
     # ---------------- dominant kernels, timed live with HIP events on the plan's stream

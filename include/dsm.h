@@ -21,7 +21,8 @@
  *  - All device work is enqueued on `stream` (a hipStream_t; NULL = the
  *    default stream).  Calls return once the work is enqueued; outputs are
  *    valid after the stream reaches that point.  A plan must not be used
- *    from two streams at once.
+ *    from two streams at once: every forward and backward rewrites the
+ *    plan's per-view constants (the light cameras) on the device.
  *  - Every call returns a dsm_status.  Arguments are validated on the host
  *    before anything is enqueued; on an error nothing is enqueued and
  *    outputs are left untouched.  No exception or abort crosses the ABI.
@@ -178,14 +179,18 @@ typedef struct {
     int64_t total_vertices;
     int64_t total_faces;
     int64_t image_floats;        /* sum over renders of H*W*C                          */
-    int64_t saved_bytes;         /* forward state kept for the backward pass           */
-    int64_t scratch_bytes;       /* temporaries of one forward or backward call        */
+    int64_t saved_bytes;         /* forward state kept for the backward pass (depth
+                                    keys, triangle setup, maps, images before smoothing,
+                                    the tile bins and the forward's counters)           */
+    int64_t scratch_bytes;       /* temporaries of one forward or backward call; nothing
+                                    in it outlives the call, so any scratch of this size
+                                    serves any call                                     */
     int64_t map_floats;          /* sum over lights of 2*S*S                           */
     int32_t tile_size;           /* raster tile side in pixels                         */
     int32_t bin_capacity_scale;  /* bin capacity = scale * (triangles + tiles) / 4     */
 } dsm_plan_info;
 
-/* Counters of the last forward pass (device-side, read back on demand). */
+/* Counters of a forward pass, kept in its saved buffer (read back on demand). */
 typedef struct {
     uint64_t culled_triangles;   /* dropped by the w > 0 / near / guard-band tests     */
     uint64_t binned_pairs;       /* (triangle, tile) pairs requested                    */
@@ -219,7 +224,8 @@ void dsm_plan_destroy(dsm_plan *plan);
  *   albedo_dev       [F_total,C] per-face albedo
  *   saved_dev        saved_bytes of caller memory, written here, read by
  *                    dsm_backward (keep it alive and unmodified in between)
- *   scratch_dev      scratch_bytes of caller memory
+ *   scratch_dev      scratch_bytes of caller memory, used only during this
+ *                    call (its contents on return are unspecified)
  *   images_dev       [image_floats]: render r's [H,W,C] image at the offset
  *                    sum_{r'<r} H W C
  */
@@ -233,7 +239,9 @@ dsm_status dsm_forward(dsm_plan *plan, const float *verts_dev, const float *ligh
  *   grad_verts_dev        [V_total,3]
  *   grad_light_params_dev [L,3]
  *   grad_albedo_dev       [F_total,C] or NULL
- * verts/light_params/albedo/saved must be those of the matching forward.
+ * verts/light_params/albedo/saved must be those of the matching forward;
+ * scratch_dev is any scratch_bytes of caller memory (it need not be the
+ * forward's: backward reads only what saved holds).
  */
 dsm_status dsm_backward(dsm_plan *plan, const float *verts_dev, const float *light_params_dev,
                         const float *albedo_dev, const void *saved_dev, size_t saved_bytes,
@@ -281,8 +289,8 @@ dsm_status dsm_get_light_maps(const dsm_plan *plan, const void *saved_dev, const
                               int32_t light, int32_t which, float *out_dev, dsm_stream stream);
 dsm_status dsm_get_render_image0(const dsm_plan *plan, const void *saved_dev, int32_t render,
                                  float *out_dev, dsm_stream stream);
-/* Counters of the last forward; synchronizes `stream`. */
-dsm_status dsm_get_stats(const dsm_plan *plan, const void *scratch_dev, dsm_stats *out, dsm_stream stream);
+/* Counters of the forward that wrote saved_dev; synchronizes `stream`. */
+dsm_status dsm_get_stats(const dsm_plan *plan, const void *saved_dev, dsm_stats *out, dsm_stream stream);
 
 /*
  * Moment filter on its own (Eq. moment1 and moment2: m = G f~ for both

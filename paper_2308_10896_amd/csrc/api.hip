@@ -461,6 +461,8 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
 
     // saved layout
     size_t o = 0;
+    p->sv_counters = o; o = align_up(o + sizeof(DevCounters));
+    p->sv_zero_end = o;
     p->sv_keys = o; o = align_up(o + 8 * (size_t)pix);
     p->sv_clip = o; o = align_up(o + 16 * (size_t)clip);
     p->sv_setup = o; o = align_up(o + sizeof(TriSetup) * (size_t)tri);
@@ -469,22 +471,21 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sv_F0 = o; o = align_up(o + 4 * (size_t)maps);
     p->sv_M = o; o = align_up(o + 4 * (size_t)fmaps);
     p->sv_img0 = o; o = align_up(o + 4 * (size_t)img);
+    p->sv_pair_off = o; o = align_up(o + 4 * ((size_t)tri + 1));
+    p->sv_tile_start = o; o = align_up(o + 4 * ((size_t)tiles + 1));
+    p->sv_bins = o; o = align_up(o + 4 * (size_t)p->capacity);
+    p->sv_bin_pair = o; o = align_up(o + 4 * (size_t)p->capacity);
+    p->sv_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->saved_bytes = std::max<size_t>(o, kAlign);
     // scratch layout
     o = 0;
-    p->sc_counters = o; o = align_up(o + sizeof(DevCounters));
     p->sc_tile_cnt = o; o = align_up(o + 4 * ((size_t)tiles + 1));
     p->sc_tile_cursor = o; o = align_up(o + 4 * ((size_t)tiles + 1));
     p->sc_zero_fwd_end = o;
     p->sc_pair_cnt = o; o = align_up(o + 4 * ((size_t)tri + 1));
-    p->sc_pair_off = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
-    p->sc_tile_start = o; o = align_up(o + 4 * ((size_t)tiles + 1));
     p->sc_facing = o; o = align_up(o + (size_t)tri + 1);
-    p->sc_bins = o; o = align_up(o + 4 * (size_t)p->capacity);
-    p->sc_bin_pair = o; o = align_up(o + 4 * (size_t)p->capacity);
     p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
-    p->sc_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_F1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
     p->sc_gimg0 = o; o = align_up(o + 4 * (size_t)img);
     p->sc_bigcount = o; o = align_up(o + 64);
@@ -623,16 +624,16 @@ const T *at(const void *base, size_t off) { return (const T *)((const char *)bas
 
 dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo, void *saved,
                            void *scratch, float *images, hipStream_t s, hipEvent_t *marks = nullptr) {
-    DevCounters *cnt = at<DevCounters>(scratch, p->sc_counters);
+    DevCounters *cnt = at<DevCounters>(saved, p->sv_counters);
     unsigned *tile_cnt = at<unsigned>(scratch, p->sc_tile_cnt);
     unsigned *tile_cursor = at<unsigned>(scratch, p->sc_tile_cursor);
     unsigned *pair_cnt = at<unsigned>(scratch, p->sc_pair_cnt);
-    unsigned *pair_off = at<unsigned>(scratch, p->sc_pair_off);
+    unsigned *pair_off = at<unsigned>(saved, p->sv_pair_off);
     unsigned *scan = at<unsigned>(scratch, p->sc_scan);
-    unsigned *tile_start = at<unsigned>(scratch, p->sc_tile_start);
-    unsigned *bins = at<unsigned>(scratch, p->sc_bins);
-    unsigned *bin_pair = at<unsigned>(scratch, p->sc_bin_pair);
-    unsigned *overflow = at<unsigned>(scratch, p->sc_overflow);
+    unsigned *tile_start = at<unsigned>(saved, p->sv_tile_start);
+    unsigned *bins = at<unsigned>(saved, p->sv_bins);
+    unsigned *bin_pair = at<unsigned>(saved, p->sv_bin_pair);
+    unsigned *overflow = at<unsigned>(saved, p->sv_overflow);
     float *F1 = at<float>(scratch, p->sc_F1);
     unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
     float4 *clip = at<float4>(saved, p->sv_clip);
@@ -644,7 +645,8 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     float *img0 = at<float>(saved, p->sv_img0);
 
     DSM_MARK(DSM_STAGE_SETUP);
-    DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));
+    DSM_TRY(zero_async(saved, p->sv_zero_end, s));                 // counters
+    DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));           // tile counts and cursors
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts,
@@ -689,13 +691,13 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     const float *F0 = at<float>(saved, p->sv_F0);
     const float *Mm = at<float>(saved, p->sv_M);
     const float *img0 = at<float>(saved, p->sv_img0);
-    const DevCounters *cnt = at<DevCounters>(scratch, p->sc_counters);
-    const unsigned *pair_off = at<unsigned>(scratch, p->sc_pair_off);
-    const unsigned *tile_start = at<unsigned>(scratch, p->sc_tile_start);
-    const unsigned *bins = at<unsigned>(scratch, p->sc_bins);
-    const unsigned *bin_pair = at<unsigned>(scratch, p->sc_bin_pair);
+    const DevCounters *cnt = at<DevCounters>(saved, p->sv_counters);
+    const unsigned *pair_off = at<unsigned>(saved, p->sv_pair_off);
+    const unsigned *tile_start = at<unsigned>(saved, p->sv_tile_start);
+    const unsigned *bins = at<unsigned>(saved, p->sv_bins);
+    const unsigned *bin_pair = at<unsigned>(saved, p->sv_bin_pair);
     unsigned char *pair_flag = at<unsigned char>(scratch, p->sc_pair_flag);
-    const unsigned *overflow = at<unsigned>(scratch, p->sc_overflow);
+    const unsigned *overflow = at<unsigned>(saved, p->sv_overflow);
     float *gimg0 = at<float>(scratch, p->sc_gimg0);
     unsigned *big_count = at<unsigned>(scratch, p->sc_bigcount);
     float *gM = at<float>(scratch, p->sc_gM);
@@ -910,10 +912,10 @@ extern "C" dsm_status dsm_get_render_image0(const dsm_plan *p, const void *saved
     return DSM_OK;
 }
 
-extern "C" dsm_status dsm_get_stats(const dsm_plan *p, const void *scratch, dsm_stats *out, dsm_stream stream) {
-    if (!p || !scratch || !out) return DSM_ERR_INVALID_ARG;
+extern "C" dsm_status dsm_get_stats(const dsm_plan *p, const void *saved, dsm_stats *out, dsm_stream stream) {
+    if (!p || !saved || !out) return DSM_ERR_INVALID_ARG;
     DevCounters c;
-    DSM_TRY(hipMemcpyAsync(&c, at<char>(scratch, p->sc_counters), sizeof(c), hipMemcpyDeviceToHost,
+    DSM_TRY(hipMemcpyAsync(&c, at<char>(saved, p->sv_counters), sizeof(c), hipMemcpyDeviceToHost,
                            (hipStream_t)stream));
     DSM_TRY(hipStreamSynchronize((hipStream_t)stream));
     out->culled_triangles = c.culled;

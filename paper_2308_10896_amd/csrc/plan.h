@@ -60,11 +60,15 @@ struct dsm_plan {
     int *light_renders_d = nullptr;
     int *scene_face_off_d = nullptr;    // [B+1]
 
-    // layout of the caller's saved buffer (byte offsets)
-    size_t sv_keys = 0, sv_clip = 0, sv_setup = 0, sv_sil = 0, sv_tv = 0, sv_F0 = 0, sv_M = 0, sv_img0 = 0, saved_bytes = 0;
-    // layout of the caller's scratch buffer (byte offsets)
-    size_t sc_counters = 0, sc_pair_cnt = 0, sc_pair_off = 0, sc_scan = 0, sc_tile_cnt = 0, sc_tile_start = 0, sc_facing = 0,
-           sc_tile_cursor = 0, sc_bins = 0, sc_bin_pair = 0, sc_pair_flag = 0, sc_overflow = 0, sc_F1 = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
+    // layout of the caller's saved buffer (byte offsets): everything the
+    // forward writes and the backward reads, the binning state included
+    size_t sv_counters = 0, sv_zero_end = 0, sv_keys = 0, sv_clip = 0, sv_setup = 0, sv_sil = 0, sv_tv = 0, sv_F0 = 0,
+           sv_M = 0, sv_img0 = 0, sv_pair_off = 0, sv_tile_start = 0, sv_bins = 0, sv_bin_pair = 0, sv_overflow = 0,
+           saved_bytes = 0;
+    // layout of the caller's scratch buffer (byte offsets): temporaries of
+    // one call, nothing carried from a forward to its backward
+    size_t sc_pair_cnt = 0, sc_scan = 0, sc_tile_cnt = 0, sc_facing = 0,
+           sc_tile_cursor = 0, sc_pair_flag = 0, sc_F1 = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
            sc_gclip = 0, sc_glight = 0, sc_zero_fwd_end = 0, sc_bigcount = 0, sc_zero_bwd_end = 0,
            sc_pair_sums = 0, sc_gtri = 0, sc_biglist = 0, sc_part_light = 0, sc_part_gm = 0, sc_part_render = 0, sc_jac = 0,
            scratch_bytes = 0;

@@ -167,6 +167,7 @@ class Plan:
         self.view_shapes = [(l.resolution, l.resolution) for l in batch.lights] + \
                            [(c.height, c.width) for c in batch.cameras]
         self.light_res = [l.resolution for l in batch.lights]
+        self._scratch = {}
 
     def __del__(self):
         h = getattr(self, 'handle', None)
@@ -182,6 +183,19 @@ class Plan:
         saved = torch.empty(int(self.info.saved_bytes), dtype=torch.uint8, device=device)
         scratch = torch.empty(int(self.info.scratch_bytes), dtype=torch.uint8, device=device)
         return saved, scratch
+
+    def scratch(self, device='cuda'):
+        """The plan's own scratch buffer on `device`, allocated on first use
+        and reused by every later call (scratch carries nothing from a forward
+        to its backward; calls on one plan are ordered on one stream)."""
+        dev = torch.device(device)
+        if dev.type == 'cuda' and dev.index is None:
+            dev = torch.device('cuda', torch.cuda.current_device())
+        t = self._scratch.get(dev)
+        if t is None:
+            t = torch.empty(int(self.info.scratch_bytes), dtype=torch.uint8, device=dev)
+            self._scratch[dev] = t
+        return t
 
     def split_images(self, flat):
         out, o = [], 0
@@ -243,9 +257,10 @@ class Plan:
         _lib.call('dsm_get_render_image0', self.handle, _ptr(saved), int(render), _ptr(out), _stream())
         return out
 
-    def stats(self, scratch):
+    def stats(self, saved):
+        """Counters of the forward that wrote `saved`."""
         st = _lib.Stats()
-        _lib.call('dsm_get_stats', self.handle, _ptr(scratch), C.byref(st), _stream())
+        _lib.call('dsm_get_stats', self.handle, _ptr(saved), C.byref(st), _stream())
         return dict(culled=st.culled_triangles, pairs=st.binned_pairs, overflow=st.overflow_triangles,
                     bad_indices=st.bad_indices)
 
@@ -296,16 +311,17 @@ def autotune(batch, verts, light_params, albedo, grad_images, reps: int = 3, cac
 class _Render(torch.autograd.Function):
     @staticmethod
     def forward(ctx, plan, verts, light_params, albedo):
-        saved, scratch = plan.workspace(verts.device)
-        images = plan.forward(verts, light_params, albedo, saved, scratch)
+        saved = torch.empty(int(plan.info.saved_bytes), dtype=torch.uint8, device=verts.device)
+        images = plan.forward(verts, light_params, albedo, saved, plan.scratch(verts.device))
         ctx.plan = plan
-        ctx.save_for_backward(verts, light_params, albedo, saved, scratch)
+        ctx.save_for_backward(verts, light_params, albedo, saved)
         return images
 
     @staticmethod
     def backward(ctx, grad_images):
-        verts, light_params, albedo, saved, scratch = ctx.saved_tensors
-        gv, gl, ga = ctx.plan.backward(verts, light_params, albedo, saved, scratch, grad_images.contiguous(),
+        verts, light_params, albedo, saved = ctx.saved_tensors
+        gv, gl, ga = ctx.plan.backward(verts, light_params, albedo, saved, ctx.plan.scratch(verts.device),
+                                       grad_images.contiguous(),
                                        want_albedo=ctx.needs_input_grad[3])
         return None, gv, gl, ga
 

@@ -35,7 +35,7 @@ def gpu_run(batch, tile_size=0, bin_scale=0, grad_images=None, pose=False):
     out['F1'] = [plan.light_maps(saved, scratch, l, 1).cpu().numpy() for l in range(plan.num_lights)]
     out['M'] = [plan.light_maps(saved, scratch, l, 2).cpu().numpy() for l in range(plan.num_lights)]
     out['img0'] = [plan.image0(saved, r).cpu().numpy() for r in range(len(batch.renders))]
-    out['stats'] = plan.stats(scratch)
+    out['stats'] = plan.stats(saved)
     out['verts'] = verts.cpu().numpy()
     if grad_images is not None:
         g = torch.as_tensor(np.concatenate([x.ravel() for x in grad_images]).astype(np.float32)).cuda()

@@ -49,7 +49,7 @@ def test_full_size_batch_sampled_scenes():
     gpose = plan.pose_backward(local, poses, gv).cpu().numpy()
     gl = gl.cpu().numpy()
     imgs = [im.cpu().numpy() for im in plan.split_images(images)]
-    st = plan.stats(scratch)
+    st = plan.stats(saved)
     assert st['culled'] == 0 and st['bad_indices'] == 0
     L = len(batch.lights)
     for i in pick:
