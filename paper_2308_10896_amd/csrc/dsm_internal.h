@@ -212,6 +212,16 @@ __device__ __forceinline__ int wave_min(int v) {
     const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
     return min(min(r0, r1), min(r2, r3));
 }
+// Maximum over the 64 lanes of a wave, returned to every lane.  All lanes active.
+__device__ __forceinline__ int wave_max(int v) {
+    v = max(v, dpp_movi<0xB1>(v));
+    v = max(v, dpp_movi<0x4E>(v));
+    v = max(v, dpp_movi<0x124>(v));
+    v = max(v, dpp_movi<0x128>(v));
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
 
 // Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each
 // XCD has its own L2.  These renumber a grid so that each XCD takes a

@@ -597,24 +597,36 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
 
 // Bilinear scatter of one light's moment-map gradient from the pixels of a
 // tile.  Each wave adds its taps into an LDS window of WIN x WIN texels
-// anchored at the smallest tap it touches, then adds the window's non-zero
-// texels to global memory: a few texels per pixel instead of eight atomics.
-// Taps outside the window go to global memory directly.  Uniform call.
+// anchored at the smallest tap it touches, then adds the non-zero values of
+// the texels its taps can reach (the taps' bounding box, clipped to the
+// window) to global memory: lit pixels carry no map gradient, so most
+// windows hold a few texels, not WIN x WIN.  Taps outside the window go to
+// global memory directly.  Uniform call.
 template <int NW, int PPT, int WIN>
 __device__ __forceinline__ void map_window_scatter(const MapHit (&hit)[PPT], int S, float *__restrict__ gmap) {
     __shared__ float win[NW][2][WIN * WIN];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int mx = 0x7fffffff, my = 0x7fffffff;
+    int mx = 0x7fffffff, my = 0x7fffffff, Mx = -1, My = -1;
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
         if (hit[k].gm1 != 0.f || hit[k].gm2 != 0.f) {
             mx = min(mx, min(max(hit[k].ix, 0), S - 1));
             my = min(my, min(max(hit[k].iy, 0), S - 1));
+            Mx = max(Mx, min(max(hit[k].ix + 1, 0), S - 1));
+            My = max(My, min(max(hit[k].iy + 1, 0), S - 1));
         }
     mx = wave_min(mx);
     my = wave_min(my);
+    Mx = wave_max(Mx);
+    My = wave_max(My);
     const bool any = mx != 0x7fffffff;
-    for (int e = lane; e < 2 * WIN * WIN; e += 64) (&win[w][0][0])[e] = 0.f;
+    // every tap that lands in the window lies in the bounding box
+    const int bw = any ? min(Mx - mx + 1, WIN) : 0, bh = any ? min(My - my + 1, WIN) : 0;
+    for (int e = lane; e < bw * bh; e += 64) {
+        const int o = (e / bw) * WIN + e % bw;
+        win[w][0][o] = 0.f;
+        win[w][1][o] = 0.f;
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -643,14 +655,15 @@ __device__ __forceinline__ void map_window_scatter(const MapHit (&hit)[PPT], int
         }
     }
     __syncthreads();
-    if (any)
-        for (int e = lane; e < WIN * WIN; e += 64) {
-            const int gx = mx + e % WIN, gy = my + e / WIN;
-            if (gx >= S || gy >= S) continue;
-            const long long o = 2 * ((long long)gy * S + gx);
-            atomic_add_f32(gmap + o, win[w][0][e]);
-            atomic_add_f32(gmap + o + 1, win[w][1][e]);
+    if (any) {
+        for (int e = lane; e < bw * bh; e += 64) {
+            const int ex = e % bw, ey = e / bw;
+            const long long o = 2 * ((long long)(my + ey) * S + (mx + ex));
+            const float a = win[w][0][ey * WIN + ex], b = win[w][1][ey * WIN + ex];
+            if (a != 0.f) atomic_add_f32(gmap + o, a);
+            if (b != 0.f) atomic_add_f32(gmap + o + 1, b);
         }
+    }
     __syncthreads();
 }
 
