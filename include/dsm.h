@@ -188,6 +188,9 @@ typedef struct {
     int64_t map_floats;          /* sum over lights of 2*S*S                           */
     int32_t tile_size;           /* raster tile side in pixels                         */
     int32_t bin_capacity_scale;  /* bin capacity = scale * (triangles + tiles) / 4     */
+    int64_t forward_scratch_bytes; /* the part of scratch a forward pass uses (at most
+                                    scratch_bytes); dsm_forward_static_scratch needs it
+                                    to be at most DSM_STATIC_SCRATCH_BYTES              */
 } dsm_plan_info;
 
 /* Counters of a forward pass, kept in its saved buffer (read back on demand). */
@@ -209,7 +212,9 @@ const char *dsm_status_string(dsm_status status);
  * tiles) / 4 (triangle, tile) pairs over all views (1..1024; 0 = default 32).
  * Triangles whose pairs do not fit are rasterized by a slower overflow path
  * with identical results.
- * The plan owns only mesh-static device data (faces, adjacency, layout).
+ * The plan owns only mesh-static device data (faces, adjacency, layout),
+ * allocated on the HIP device current at this call; later calls with the
+ * plan run with that device current.
  */
 dsm_status dsm_plan_create(const dsm_batch_desc *desc, int32_t tile_size, int32_t bin_capacity_scale,
                            dsm_plan **out_plan);
@@ -232,6 +237,27 @@ void dsm_plan_destroy(dsm_plan *plan);
 dsm_status dsm_forward(dsm_plan *plan, const float *verts_dev, const float *light_params_dev,
                        const float *albedo_dev, void *saved_dev, size_t saved_bytes,
                        void *scratch_dev, size_t scratch_bytes, float *images_dev, dsm_stream stream);
+
+/*
+ * dsm_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc): the same
+ * kernels and results, with the forward's temporaries in a library-owned
+ * device array of DSM_STATIC_SCRATCH_BYTES per GPU (held from the library's
+ * load until the process ends) instead of a caller scratch buffer.  The
+ * caller still owns verts, light_params, albedo, saved and images, with the
+ * meanings and layouts of dsm_forward; dsm_backward then takes any scratch
+ * buffer of scratch_bytes, as after dsm_forward.  The call allocates nothing.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU (two streams, two host threads) race: order them on one stream.
+ * Errors: DSM_ERR_WORKSPACE_TOO_SMALL when the plan's forward_scratch_bytes
+ * exceed DSM_STATIC_SCRATCH_BYTES or saved_bytes is below the plan's;
+ * DSM_ERR_INVALID_ARG for null or misaligned buffers, or when the current
+ * device is not the one the plan was created on; otherwise as dsm_forward.
+ */
+#define DSM_STATIC_SCRATCH_BYTES (64ull << 20)
+dsm_status dsm_forward_static_scratch(dsm_plan *plan, const float *verts_dev, const float *light_params_dev,
+                                      const float *albedo_dev, void *saved_dev, size_t saved_bytes,
+                                      float *images_dev, dsm_stream stream);
 
 /*
  * Reverse pass of dsm_forward for upstream image gradient grad_images_dev

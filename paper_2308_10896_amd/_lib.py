@@ -58,7 +58,8 @@ class BatchDesc(C.Structure):
 class PlanInfo(C.Structure):
     _fields_ = [('total_vertices', C.c_int64), ('total_faces', C.c_int64), ('image_floats', C.c_int64),
                 ('saved_bytes', C.c_int64), ('scratch_bytes', C.c_int64), ('map_floats', C.c_int64),
-                ('tile_size', C.c_int32), ('bin_capacity_scale', C.c_int32)]
+                ('tile_size', C.c_int32), ('bin_capacity_scale', C.c_int32),
+                ('forward_scratch_bytes', C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -78,6 +79,7 @@ _SIGNATURES = {
     'dsm_plan_info_get': (C.c_int, [P, C.POINTER(PlanInfo)]),
     'dsm_plan_destroy': (None, [P]),
     'dsm_forward': (C.c_int, [P, P, P, P, P, SZ, P, SZ, P, P]),
+    'dsm_forward_static_scratch': (C.c_int, [P, P, P, P, P, SZ, P, P]),
     'dsm_backward': (C.c_int, [P, P, P, P, P, SZ, P, SZ, P, P, P, P, P]),
     'dsm_pose_forward': (C.c_int, [P, P, P, P, P]),
     'dsm_pose_backward': (C.c_int, [P, P, P, P, P, P]),

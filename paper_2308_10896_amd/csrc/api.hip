@@ -248,10 +248,12 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
         }
     }
 
-    int ndev = 0;
+    int ndev = 0, dev = -1;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return DSM_ERR_NO_DEVICE;
+    if (hipGetDevice(&dev) != hipSuccess) return DSM_ERR_HIP;
     dsm_plan *p = new (std::nothrow) dsm_plan();
     if (!p) return DSM_ERR_OUT_OF_MEMORY;
+    p->device = dev;
     p->B = B; p->L = L; p->Cm = Cm; p->R = R; p->C = d->channels; p->nviews = L + Cm;
     p->camera_antialias = d->camera_antialias != 0;
     p->V_total = Vt; p->F_total = Ft;
@@ -485,8 +487,9 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_pair_cnt = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
     p->sc_facing = o; o = align_up(o + (size_t)tri + 1);
-    p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
     p->sc_F1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
+    p->sc_fwd_end = o;                 // the forward touches nothing past this
+    p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
     p->sc_gimg0 = o; o = align_up(o + 4 * (size_t)img);
     p->sc_bigcount = o; o = align_up(o + 64);
     p->sc_gM = o; o = align_up(o + 4 * (size_t)fmaps);
@@ -598,6 +601,7 @@ extern "C" dsm_status dsm_plan_info_get(const dsm_plan *p, dsm_plan_info *out) {
     out->image_floats = p->image_floats;
     out->saved_bytes = (int64_t)p->saved_bytes;
     out->scratch_bytes = (int64_t)p->scratch_bytes;
+    out->forward_scratch_bytes = (int64_t)p->sc_fwd_end;
     out->map_floats = p->map_floats;
     out->tile_size = p->tile;
     out->bin_capacity_scale = p->bin_scale;
@@ -767,6 +771,20 @@ extern "C" dsm_status dsm_forward(dsm_plan *p, const float *verts, const float *
         return DSM_ERR_INVALID_ARG;
     return enqueue_forward(p, verts, lparams, albedo, saved, scratch, images, (hipStream_t)stream);
 }
+
+namespace dsm {
+dsm_status forward_in_scratch(dsm_plan *p, const float *verts, const float *lparams, const float *albedo, void *saved,
+                              size_t saved_bytes, void *scratch, size_t scratch_bytes, float *images,
+                              hipStream_t stream) {
+    if (!p || !saved || !scratch) return DSM_ERR_INVALID_ARG;
+    if (saved_bytes < p->saved_bytes || scratch_bytes < p->sc_fwd_end) return DSM_ERR_WORKSPACE_TOO_SMALL;
+    if (((uintptr_t)saved & 255) || ((uintptr_t)scratch & 255)) return DSM_ERR_INVALID_ARG;
+    if ((p->V_total > 0 && !verts) || (p->L > 0 && !lparams) || (p->F_total > 0 && !albedo) ||
+        (p->image_floats > 0 && !images))
+        return DSM_ERR_INVALID_ARG;
+    return enqueue_forward(p, verts, lparams, albedo, saved, scratch, images, stream);
+}
+}  // namespace dsm
 
 extern "C" dsm_status dsm_backward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
                                    const void *saved, size_t saved_bytes, void *scratch, size_t scratch_bytes,

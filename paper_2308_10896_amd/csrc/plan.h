@@ -9,6 +9,7 @@
 
 struct dsm_plan {
     // batch shape
+    int device = -1;   // HIP device current at creation; the plan's device data live there
     int B = 0, L = 0, Cm = 0, R = 0, C = 1, nviews = 0;
     int camera_antialias = 1;
     long long V_total = 0, F_total = 0;
@@ -68,7 +69,7 @@ struct dsm_plan {
     // layout of the caller's scratch buffer (byte offsets): temporaries of
     // one call, nothing carried from a forward to its backward
     size_t sc_pair_cnt = 0, sc_scan = 0, sc_tile_cnt = 0, sc_facing = 0,
-           sc_tile_cursor = 0, sc_pair_flag = 0, sc_F1 = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
+           sc_tile_cursor = 0, sc_pair_flag = 0, sc_F1 = 0, sc_fwd_end = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
            sc_gclip = 0, sc_glight = 0, sc_zero_fwd_end = 0, sc_bigcount = 0, sc_zero_bwd_end = 0,
            sc_pair_sums = 0, sc_gtri = 0, sc_biglist = 0, sc_part_light = 0, sc_part_gm = 0, sc_part_render = 0, sc_jac = 0,
            scratch_bytes = 0;
@@ -76,3 +77,12 @@ struct dsm_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
+
+namespace dsm {
+// The forward pass with a scratch buffer that need only hold the forward's
+// temporaries (plan->sc_fwd_end bytes): validates its arguments as
+// dsm_forward does and enqueues the same kernels on `stream`.
+dsm_status forward_in_scratch(dsm_plan *p, const float *verts, const float *lparams, const float *albedo, void *saved,
+                              size_t saved_bytes, void *scratch, size_t scratch_bytes, float *images,
+                              hipStream_t stream);
+}  // namespace dsm
