@@ -305,8 +305,14 @@ dsm_status dsm_graph_launch(dsm_plan *plan, dsm_stream stream);
  *  dsm_get_view_keys: 64-bit depth|triangle keys of view v (lights first,
  *      then cameras; ~0 = background) -> [H,W] uint64.
  *  dsm_get_light_maps: which = 0 unsmoothed (z, z^2), 1 smoothed, 2 filtered
- *      moments (m1, m2) -> [2,S,S].  which = 1 needs scratch of the forward
- *      still intact (it is not part of the saved state).
+ *      moments (m1, m2) -> [2,S,S], of z = d / zfar (exponential maps:
+ *      exp(c z), exp(2 c z)).  Internally the maps hold the same quantities
+ *      of z - zc, zc a per-light reference depth (the depth of the light's
+ *      look-at point; 0 for cube faces) kept in saved, which leaves
+ *      m2 - m1^2 and d - m1 unchanged and keeps more float32 digits of the
+ *      variance; the getter converts back.  saved is needed for every
+ *      `which`; which = 1 also needs scratch of the forward still intact
+ *      (it is not part of the saved state).
  *  dsm_get_render_image0: shaded image of render r before border smoothing.
  */
 dsm_status dsm_get_view_keys(const dsm_plan *plan, const void *saved_dev, int32_t view,
@@ -331,7 +337,7 @@ dsm_status dsm_filter_moments(int32_t S, int32_t n_maps, int32_t filter, int32_t
 /*
  * Stage timing (instrumentation, not part of the method).  The pipeline's
  * stages in launch order; a stage's time runs from its first launch to the
- * next stage's first launch on the stream.
+ * end of its last launch on the stream.
  */
 typedef enum {
     DSM_STAGE_SETUP = 0,        /* zero fills, light frames, transform, triangle setup, silhouette masks */
@@ -355,19 +361,25 @@ typedef enum {
 
 /*
  * Runs dsm_forward + dsm_backward `reps` times on `stream` (arguments as
- * there) with a HIP event at every stage boundary, waits for the stream, and
- * writes each stage's mean duration in milliseconds to ms_out (host,
- * [DSM_STAGE_COUNT]).  `stream` must be a non-null stream that is not being
- * captured.  Outputs are those of the last repetition.  Errors:
- * DSM_ERR_INVALID_ARG for a null plan/ms_out/stream or reps outside
- * [1, DSM_MAX_TIMING_REPS]; buffer errors as dsm_forward; DSM_ERR_HIP when an
- * event cannot be created, recorded or read.
+ * there) with a HIP event at the start and at the end of every stage, waits
+ * for the stream, and writes each stage's mean duration in milliseconds to
+ * ms_out (host, [DSM_STAGE_COUNT]).  flush_dev (nullable): flush_bytes of
+ * device memory that the timer overwrites after every stage ends and before
+ * the next starts (outside the timed intervals), so that each stage starts
+ * with cold caches (give it more than the GPU's last-level cache, e.g.
+ * 1 GiB); NULL times the stages back to back, each finding what the
+ * previous one left in the caches.  `stream` must be a non-null stream that
+ * is not being captured.  Outputs are those of the last repetition.  Errors:
+ * DSM_ERR_INVALID_ARG for a null plan/ms_out/stream, reps outside
+ * [1, DSM_MAX_TIMING_REPS], or a flush buffer that is misaligned or under 4
+ * bytes; buffer errors as dsm_forward; DSM_ERR_HIP when an event cannot be
+ * created, recorded or read.
  */
 dsm_status dsm_time_stages(dsm_plan *plan, const float *verts_dev, const float *light_params_dev,
                            const float *albedo_dev, void *saved_dev, size_t saved_bytes, void *scratch_dev,
                            size_t scratch_bytes, float *images_dev, const float *grad_images_dev,
                            float *grad_verts_dev, float *grad_light_params_dev, float *grad_albedo_dev,
-                           int32_t reps, float *ms_out, dsm_stream stream);
+                           int32_t reps, void *flush_dev, size_t flush_bytes, float *ms_out, dsm_stream stream);
 
 /*
  * Autotuner for the plan's tile side and bin depth (dsm_plan_create's

@@ -92,7 +92,7 @@ _SIGNATURES = {
     'dsm_filter_moments': (C.c_int, [I32, I32, I32, I32, F32, P, P, I32, P]),
     'dsm_autotune': (C.c_int, [C.POINTER(BatchDesc), P, P, P, P, I32, C.c_char_p, P, C.POINTER(I32),
                                C.POINTER(I32), C.POINTER(C.c_float)]),
-    'dsm_time_stages': (C.c_int, [P, P, P, P, P, SZ, P, SZ, P, P, P, P, P, I32, C.POINTER(C.c_float), P]),
+    'dsm_time_stages': (C.c_int, [P, P, P, P, P, SZ, P, SZ, P, P, P, P, P, I32, P, SZ, C.POINTER(C.c_float), P]),
 }
 
 _lib = None

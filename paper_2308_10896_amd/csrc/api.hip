@@ -115,14 +115,37 @@ __global__ void zero_kernel(unsigned *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
-// Filtered maps are stored (m1, m2) interleaved per texel, side S + 2P with
-// the face at offset P; the getter hands out the two planes of the face.
-__global__ void deinterleave_kernel(const float *src, int S, int sp, int P, float *out) {
+// A light's maps as the getter hands them out: two planes of S x S texels
+// holding (f, f^2) of z = d / zfar (or exp(c z), exp(2 c z)).  The library
+// stores moments of z - zc (zc: the light's reference depth, kept in saved),
+// which an affine map turns back: f = f' + zc, f^2 = f^2' + zc (2 f' + zc),
+// or for exponential maps f = f' e^{c zc}, f^2 = f^2' e^{2 c zc}.  Filtered
+// maps are stored (m1, m2) interleaved per texel with side S + 2P (the face
+// at offset P); the others are planar with side S.
+__global__ void light_maps_out_kernel(const float *src, int S, int sp, int P, bool interleaved, const float *zc_p,
+                                      float warp_c, float *out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= S * S) return;
-    const long long q = 2 * ((long long)(t / S + P) * sp + (t % S + P));
-    out[t] = src[q];
-    out[(long long)S * S + t] = src[q + 1];
+    const float zc = *zc_p;
+    float a, b;
+    if (interleaved) {
+        const long long q = 2 * ((long long)(t / S + P) * sp + (t % S + P));
+        a = src[q];
+        b = src[q + 1];
+    } else {
+        a = src[t];
+        b = src[(long long)S * S + t];
+    }
+    if (warp_c > 0.f) {
+        const float e = expf(warp_c * zc);
+        a *= e;
+        b *= e * e;
+    } else {
+        b = b + zc * (2.f * a + zc);
+        a = a + zc;
+    }
+    out[t] = a;
+    out[(long long)S * S + t] = b;
 }
 
 hipError_t zero_async(void *p, size_t bytes, hipStream_t s) {
@@ -478,6 +501,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sv_bins = o; o = align_up(o + 4 * (size_t)p->capacity);
     p->sv_bin_pair = o; o = align_up(o + 4 * (size_t)p->capacity);
     p->sv_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
+    p->sv_zc = o; o = align_up(o + 4 * (size_t)std::max(L, 1));
     p->saved_bytes = std::max<size_t>(o, kAlign);
     // scratch layout
     o = 0;
@@ -620,14 +644,31 @@ T *at(void *base, size_t off) { return (T *)((char *)base + off); }
 template <class T>
 const T *at(const void *base, size_t off) { return (const T *)((const char *)base + off); }
 
-// marks (nullable): events recorded at stage boundaries; marks[i] opens stage i.
+// Stage timing (nullable): ev[2i] opens stage i, ev[2i + 1] closes it.  With
+// a flush buffer, flush_bytes of it are overwritten after a stage closes
+// and before the next one opens, so every stage starts with cold caches.
+struct StageMarks {
+    hipEvent_t *ev;
+    void *flush;
+    size_t flush_bytes;
+};
+dsm_status stage_mark(const StageMarks *m, int i, hipStream_t s) {
+    if (!m) return DSM_OK;
+    if (i > 0) DSM_TRY(hipEventRecord(m->ev[2 * (i - 1) + 1], s));
+    if (i < DSM_STAGE_COUNT) {
+        if (m->flush) DSM_TRY(zero_async(m->flush, m->flush_bytes, s));
+        DSM_TRY(hipEventRecord(m->ev[2 * i], s));
+    }
+    return DSM_OK;
+}
 #define DSM_MARK(i)                                                      \
     do {                                                                 \
-        if (marks) DSM_TRY(hipEventRecord(marks[(i)], s));              \
+        const dsm_status mark_st_ = stage_mark(marks, (i), s);          \
+        if (mark_st_ != DSM_OK) return mark_st_;                        \
     } while (0)
 
 dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo, void *saved,
-                           void *scratch, float *images, hipStream_t s, hipEvent_t *marks = nullptr) {
+                           void *scratch, float *images, hipStream_t s, const StageMarks *marks = nullptr) {
     DevCounters *cnt = at<DevCounters>(saved, p->sv_counters);
     unsigned *tile_cnt = at<unsigned>(scratch, p->sc_tile_cnt);
     unsigned *tile_cursor = at<unsigned>(scratch, p->sc_tile_cursor);
@@ -651,7 +692,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_MARK(DSM_STAGE_SETUP);
     DSM_TRY(zero_async(saved, p->sv_zero_end, s));                 // counters
     DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));           // tile counts and cursors
-    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, s));
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, at<float>(saved, p->sv_zc), s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts,
                              albedo, p->C, tv, s));
@@ -686,7 +727,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
 
 dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
                             const void *saved, void *scratch, const float *gimg, float *gverts, float *glparams,
-                            float *galbedo, hipStream_t s, hipEvent_t *marks = nullptr) {
+                            float *galbedo, hipStream_t s, const StageMarks *marks = nullptr) {
     const unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
     const float4 *clip = at<float4>(saved, p->sv_clip);
     const TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
@@ -717,8 +758,10 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
 
     DSM_MARK(DSM_STAGE_BWD_SETUP);
     DSM_TRY(zero_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, s));   // big count, gM, silhouette gclip
+    // pair flags: the camera tile walks set only the flags of pairs that got a sum
+    DSM_TRY(zero_async(pair_flag, ((size_t)p->capacity + 3) & ~(size_t)3, s));
     DSM_TRY(launch_overflow_rows_zero(overflow, cnt, gtri, s));
-    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, jac, s));
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, jac, nullptr, s));
     DSM_MARK(DSM_STAGE_CAMERA_AA_ADJ);
     DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
                                       verts, keys, img0, gimg, gimg0, gclip, p->C, s));
@@ -726,7 +769,8 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_TRY(launch_lookup_backward(p->tile, p->views_d, p->L, p->Cm, p->max_cam_tiles, p->max_lights_per_render,
                                    p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
                                    p->faces_d, verts, albedo, tv, keys, Mm, gimg0, gM, setup, tile_start, bins,
-                                   bin_pair, pair_flag, pair_sums, gtri, part_render, p->C, jac, s));
+                                   bin_pair, pair_flag, pair_sums, gtri, part_render, p->C, jac, pair_off,
+                                   p->capacity, s));
     DSM_MARK(DSM_STAGE_FILTER_ADJ);
     for (const auto &g : p->blur_groups)
         DSM_TRY(launch_blur(p->blur_jobs_d + p->L + g.first, g.n, g.tiles, gM, gF1, true, g.R, s));
@@ -803,31 +847,33 @@ extern "C" dsm_status dsm_backward(dsm_plan *p, const float *verts, const float 
 extern "C" dsm_status dsm_time_stages(dsm_plan *p, const float *verts, const float *lparams, const float *albedo,
                                       void *saved, size_t saved_bytes, void *scratch, size_t scratch_bytes,
                                       float *images, const float *gimg, float *gverts, float *glparams,
-                                      float *galbedo, int32_t reps, float *ms_out, dsm_stream stream) {
+                                      float *galbedo, int32_t reps, void *flush, size_t flush_bytes, float *ms_out,
+                                      dsm_stream stream) {
     if (!p || !ms_out || reps < 1 || reps > DSM_MAX_TIMING_REPS || !stream) return DSM_ERR_INVALID_ARG;
+    if (flush && (flush_bytes < 4 || ((uintptr_t)flush & 3))) return DSM_ERR_INVALID_ARG;
     dsm_status st;
     if (!buffers_ok(p, saved, saved_bytes, scratch, scratch_bytes, &st)) return st;
     if ((p->V_total > 0 && (!verts || !gverts)) || (p->L > 0 && (!lparams || !glparams)) ||
         (p->F_total > 0 && !albedo) || (p->image_floats > 0 && (!images || !gimg)))
         return DSM_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    constexpr int NE = DSM_STAGE_COUNT + 1;
+    constexpr int NE = 2 * DSM_STAGE_COUNT;
     std::vector<hipEvent_t> ev((size_t)reps * NE, nullptr);
     dsm_status r = DSM_OK;
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) { e = nullptr; r = DSM_ERR_HIP; break; }
     for (int i = 0; i < reps && r == DSM_OK; ++i) {
-        hipEvent_t *m = ev.data() + (size_t)i * NE;
-        r = enqueue_forward(p, verts, lparams, albedo, saved, scratch, images, s, m);
+        const StageMarks m{ev.data() + (size_t)i * NE, flush, flush ? flush_bytes : 0};
+        r = enqueue_forward(p, verts, lparams, albedo, saved, scratch, images, s, &m);
         if (r == DSM_OK)
-            r = enqueue_backward(p, verts, lparams, albedo, saved, scratch, gimg, gverts, glparams, galbedo, s, m);
+            r = enqueue_backward(p, verts, lparams, albedo, saved, scratch, gimg, gverts, glparams, galbedo, s, &m);
     }
     if (r == DSM_OK && hipStreamSynchronize(s) != hipSuccess) r = DSM_ERR_HIP;
     for (int k = 0; k < DSM_STAGE_COUNT; ++k) ms_out[k] = 0.f;
     for (int i = 0; i < reps && r == DSM_OK; ++i)
         for (int k = 0; k < DSM_STAGE_COUNT; ++k) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev[(size_t)i * NE + k], ev[(size_t)i * NE + k + 1]) != hipSuccess) {
+            if (hipEventElapsedTime(&ms, ev[(size_t)i * NE + 2 * k], ev[(size_t)i * NE + 2 * k + 1]) != hipSuccess) {
                 r = DSM_ERR_HIP;
                 break;
             }
@@ -909,15 +955,13 @@ extern "C" dsm_status dsm_get_light_maps(const dsm_plan *p, const void *saved, c
     const ViewConst &v = p->views_h[light];
     const size_t base = which == 0 ? p->sv_F0 : which == 1 ? p->sc_F1 : p->sv_M;
     const void *src = which == 1 ? scratch : saved;
-    if (which == 2) {
-        // the face itself (without texels sampled from cube neighbours), as two planes
-        hipLaunchKernelGGL(deinterleave_kernel, dim3((v.W * v.W + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                           at<float>(src, base + 4 * (size_t)v.fmap_off), v.W, v.W + 2 * v.fpad, v.fpad, out);
-        DSM_TRY(hipGetLastError());
-        return DSM_OK;
-    }
-    DSM_TRY(hipMemcpyAsync(out, at<char>(src, base + 4 * (size_t)v.map_off), 8 * (size_t)v.W * v.W,
-                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    if (!saved) return DSM_ERR_INVALID_ARG;       // holds the light's reference depth
+    const bool il = which == 2;
+    // filtered maps: the face itself, without the texels sampled from cube neighbours
+    hipLaunchKernelGGL(light_maps_out_kernel, dim3((v.W * v.W + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       at<float>(src, base + 4 * (size_t)(il ? v.fmap_off : v.map_off)), v.W,
+                       il ? v.W + 2 * v.fpad : v.W, il ? v.fpad : 0, il, at<float>(saved, p->sv_zc + 4 * (size_t)light), v.warp_c, out);
+    DSM_TRY(hipGetLastError());
     return DSM_OK;
 }
 

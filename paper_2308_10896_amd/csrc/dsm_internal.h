@@ -49,6 +49,7 @@ struct ViewConst {
     int cube_nb[4];     // cube faces, per map edge (left, right, top, bottom): neighbour face
                         // | its edge << 3 | (indices along the edge reversed) << 5
     int ring_off;       // cube faces: first CubeTap of this face's padding (4 P S entries)
+    float zc;           // light views: reference depth; maps hold moments of z - zc (see light_depth)
 };
 
 // One padded texel of a cube face beyond one of its edges: the bilinear
@@ -282,7 +283,7 @@ struct CamStatic;
 // Jacobian of a light frame (M[16], pos[3], dir[3]) w.r.t. its three parameter components, [22][3].
 constexpr int kJac = 66;
 hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
-                               hipStream_t s);
+                               float *zc_out, hipStream_t s);
 hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
                             hipStream_t s);
 hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj,
@@ -327,7 +328,7 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
                                   const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
                                   float *pair_sums, float *gtri, float *part_render, int C, const float *jac,
-                                  hipStream_t s);
+                                  const unsigned *pair_off, unsigned capacity, hipStream_t s);
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const unsigned char *silm, const float *verts, const TriVerts *tv,
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,

@@ -150,4 +150,20 @@ __host__ __device__ inline void light_frame(const CamStatic &c, const T p[3], T 
     }
 }
 
+// Reference depth of a light's maps (normalized by zfar): the depth of the
+// point its camera looks at (directional: the origin at dir_distance; point
+// and spot lights: the target).  The maps store moments of z - zc instead of
+// z: the variance m2 - m1^2 and every difference d - mu are unchanged, but
+// the stored values are small where the scene lies near the reference, so
+// float32 keeps more of the digits that m2 - m1^2 cancels.  Cube faces keep
+// zc = 0: their seam padding mixes the six faces' maps, which must share one
+// reference, and no single depth fits every direction.
+template <class T>
+__host__ __device__ inline double light_reference_depth(const CamStatic &c, const T p[3]) {
+    if (c.kind == 0) return c.dir_distance / c.zfar;
+    if (c.kind == 4) return 0.0;
+    const double dx = c.target[0] - (double)p[0], dy = c.target[1] - (double)p[1], dz = c.target[2] - (double)p[2];
+    return sqrt(dx * dx + dy * dy + dz * dz) / c.zfar;
+}
+
 }  // namespace dsm

@@ -358,6 +358,84 @@ __device__ __forceinline__ void overflow_rows(const ViewConst &v, const int (&ke
     }
 }
 
+// Per-(triangle, tile) sums of one 8x8 tile held by one wave, without walking
+// the tile's bin: the pairs of triangle t are the tiles of its bounding box
+// in row-major order, numbered from pair_off[t] as the binning numbers them,
+// so a pixel finds its row from its triangle's setup record.  Lanes holding
+// the same triangle are grouped by a leader loop (one iteration per distinct
+// triangle in the wave); a group of 16 or more lanes (a large ground
+// polygon) is summed with one multi-value wave reduction, the others with
+// LDS atomics into the row of their leader (the group's lowest lane), which
+// then stores the row and flags the pair.  Pair flags start at zero (the
+// backward clears them), so pairs without a pixel keep flag 0.  Pixels of
+// triangles that overflowed the bins stay unmatched for overflow_rows.
+// Uniform call (all 64 lanes).
+template <int T, int N>
+__device__ __forceinline__ void wave_pair_sums(const ViewConst &v, int tx, int ty, int key, const float (&val)[N],
+                                               bool act, bool &matched, const TriSetup *__restrict__ setup,
+                                               const unsigned *__restrict__ pair_off, unsigned capacity,
+                                               unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums) {
+    __shared__ float part[64 * N];
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned slot = 0;
+    bool mine = false;
+    if (act && key >= 0) {
+        const int si = v.setup_off + key;
+        const unsigned a = pair_off[si], b = pair_off[si + 1];
+        if (!(b > capacity && b > a)) {                  // else: the overflow path
+            const TriSetup &st = setup[si];
+            const int tx0 = st.bx0 / T, ty0 = st.by0 / T, ntx = st.bx1 / T - tx0 + 1;
+            slot = a + (unsigned)((ty - ty0) * ntx + (tx - tx0));
+            mine = true;
+        }
+    }
+    matched = mine;
+    // leader of every lane's group; groups of 16 or more lanes go to the wave reduction
+    int leader = lane;
+    unsigned long long pending = __ballot(mine), big = 0ull;
+    while (pending) {
+        const int l = __ffsll(pending) - 1;
+        const int kk = __builtin_amdgcn_readlane(key, l);
+        const bool in = mine && key == kk;
+        const unsigned long long m = __ballot(in);
+        pending &= ~m;
+        if (in) leader = l;
+        if (__popcll(m) >= 16) big |= m;
+    }
+    while (big) {
+        const int l = __ffsll(big) - 1;
+        const int kk = __builtin_amdgcn_readlane(key, l);
+        const bool in = mine && key == kk;
+        big &= ~__ballot(in);
+        float masked[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) masked[i] = in ? val[i] : 0.f;
+        const float t = wave_sum_multi(masked);          // lane 2i: the group's total of value i
+        const unsigned sl = (unsigned)__builtin_amdgcn_readlane((int)slot, l);
+        if ((lane & 1) == 0 && (lane >> 1) < N) pair_sums[(size_t)sl * kNV + (lane >> 1)] = t;
+        if (lane == l) pair_flag[sl] = 1;
+        mine = mine && !in;
+    }
+    const bool lead = mine && leader == lane;
+    if (lead) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) part[lane * N + i] = val[i];
+    }
+    __syncthreads();
+    if (mine && !lead) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (val[i] != 0.f) atomicAdd(part + leader * N + i, val[i]);
+    }
+    __syncthreads();
+    if (lead) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) pair_sums[(size_t)slot * kNV + i] = part[lane * N + i];
+        pair_flag[slot] = 1;
+    }
+    __syncthreads();
+}
+
 // ----------------------------------------------------------------------------- lookup^T
 
 // Gradient contributions of one camera pixel: vertex terms (gv[9] for the
@@ -450,7 +528,7 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                 const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
                 depth = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
             }
-            zz = depth / l.zfar;
+            zz = depth / l.zfar - l.zc;
             warp_receiver(l, zz, zw, floor_v);
             var = fmaxf(m2 - m1 * m1, floor_v);
             dd = zw - m1;
@@ -676,15 +754,19 @@ __device__ __forceinline__ void lookup_backward_body(
     const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
     const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
-    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac) {
+    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac,
+    const unsigned *__restrict__ pair_off, unsigned capacity) {
     using TS = TileShape<T>;
+    // one wave per 8x8 tile: pair rows found from the setup records (wave_pair_sums)
+    constexpr bool kWavePairs = T == 8;
     const Blk blk = xcd_block2();
     const int cam = blk.y;
     const ViewConst &cv = views[L + cam];
     const int lt = blk.x;
     if (lt >= cv.tiles_x * cv.tiles_y) return;     // whole workgroup
     const int gt = cv.tile_off + lt;
-    const BinHead head = bin_head(gt, (int)threadIdx.x, tile_start, bins, bin_pair);
+    BinHead head{};
+    if (!kWavePairs) head = bin_head(gt, (int)threadIdx.x, tile_start, bins, bin_pair);
     const int tx = lt % cv.tiles_x, ty = lt / cv.tiles_x;
     const int tid = threadIdx.x;
     int key[TS::PPT], pi[TS::PPT], pj[TS::PPT];
@@ -747,7 +829,11 @@ __device__ __forceinline__ void lookup_backward_body(
             block_sum_store<TS::NW>(accl[q], part_render + R.part_off + ((long long)q * ntiles + lt) * 3);
         }
     }
-    tile_pair_sums<T, kNV>(cv, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
+    if constexpr (kWavePairs)
+        wave_pair_sums<T, kNV>(cv, tx, ty, key[0], val[0], act[0], matched[0], setup, pair_off, capacity, pair_flag,
+                               pair_sums);
+    else
+        tile_pair_sums<T, kNV>(cv, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(cv, key, val, act, matched, gtri);
 }
 
@@ -760,8 +846,9 @@ __global__ __launch_bounds__(256) void lookup_backward_kernel(
     const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
     const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
-    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac) {
-    lookup_backward_body<T, MAXL>(views, L, renders, cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0, gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac);
+    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac,
+    const unsigned *__restrict__ pair_off, unsigned capacity) {
+    lookup_backward_body<T, MAXL>(views, L, renders, cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0, gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac, pair_off, capacity);
 }
 
 // One light per render at 8x8 or 16x16 tiles: capped at 128 VGPRs (4 waves
@@ -775,8 +862,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void l
     const float *__restrict__ maps, const float *__restrict__ gimg0, float *__restrict__ gmaps,
     const TriSetup *__restrict__ setup, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
-    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac) {
-    lookup_backward_body<T, 1>(views, L, renders, cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0, gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac);
+    float *__restrict__ gtri, float *__restrict__ part_render, int C, const float *__restrict__ jac,
+    const unsigned *__restrict__ pair_off, unsigned capacity) {
+    lookup_backward_body<T, 1>(views, L, renders, cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0, gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac, pair_off, capacity);
 }
 
 // ----------------------------------------------------------------------------- light smoothing^T + resolve^T
@@ -1216,17 +1304,19 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const float *gimg0, float *gmaps, const TriSetup *setup, const unsigned *tile_start,
                                   const unsigned *bins, const unsigned *bin_pair, unsigned char *pair_flag,
                                   float *pair_sums, float *gtri, float *part_render, int C, const float *jac,
-                                  hipStream_t s) {
+                                  const unsigned *pair_off, unsigned capacity, hipStream_t s) {
     if (Cm == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, Cm);
 #define DSM_LB1(TT)                                                                                                 \
     hipLaunchKernelGGL((lookup_backward_kernel_1l<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,     \
                        cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0,     \
-                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac)
+                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac, \
+                       pair_off, capacity)
 #define DSM_LB(TT, ML)                                                                                              \
     hipLaunchKernelGGL((lookup_backward_kernel<TT, ML>), grid, dim3(TileShape<TT>::NT), 0, s, views, L, renders,   \
                        cam_renders_off, cam_renders, render_lights, faces, verts, albedo, tv, keys, maps, gimg0,     \
-                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac)
+                       gmaps, setup, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri, part_render, C, jac, \
+                       pair_off, capacity)
 #define DSM_LB_T(TT)                                                  \
     if (max_lights <= 1 && TT <= 16) DSM_LB1(TT);                     \
     else if (max_lights <= 1) DSM_LB(TT, 1);                          \

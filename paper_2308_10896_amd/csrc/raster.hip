@@ -27,7 +27,8 @@ namespace dsm {
 
 // One thread per light: the light camera from its float32 parameter, in
 // float64, rounded to float32 for the rest of the pipeline.
-__global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L) {
+__global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L,
+                                    float *zc_out) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L) return;
     const double p[3] = {params[3 * l], params[3 * l + 1], params[3 * l + 2]};
@@ -39,6 +40,8 @@ __global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, con
         v.pos[i] = (float)pos[i];
         v.dir[i] = (float)dir[i];
     }
+    v.zc = (float)light_reference_depth(cams[l], p);
+    if (zc_out) zc_out[l] = v.zc;
 }
 
 // The Jacobian of (M[16], pos[3], dir[3]) with respect to the three
@@ -577,9 +580,9 @@ __global__ void overflow_count_kernel(DevCounters *counters) {
 // ----------------------------------------------------------------------------- host launchers
 
 hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
-                               hipStream_t s) {
+                               float *zc_out, hipStream_t s) {
     if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L);
+    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L, zc_out);
     if (jac) hipLaunchKernelGGL(light_jacobian_kernel, dim3((L + 63) / 64), dim3(64), 0, s, cams, params, L, jac);
     return hipGetLastError();
 }

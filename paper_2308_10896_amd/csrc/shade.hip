@@ -61,7 +61,7 @@ __device__ __forceinline__ float light_depth(const ViewConst &l, float x, float 
         const float dx = x - l.pos[0], dy = y - l.pos[1], dz = z - l.pos[2];
         d = sqrtf((dx * dx + dy * dy) + dz * dz);
     }
-    return d / l.zfar;
+    return d / l.zfar - l.zc;
 }
 
 // ----------------------------------------------------------------------------- resolve
@@ -73,7 +73,7 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVer
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= S * S) return;
     const unsigned long long key = keys[l.pix_off + t];
-    float z = 1.0f, z2 = 1.0f;
+    float z = 1.0f - l.zc, z2;          // background: the far plane
     if (key != kBgKey) {
         const int tri = (int)(unsigned)key;
         const TriVerts r = tv[l.face_off + tri];

@@ -277,14 +277,17 @@ class Plan:
         _lib.call('dsm_graph_launch', self.handle, C.c_void_p(stream.cuda_stream))
 
     def time_stages(self, stream, verts, light_params, albedo, saved, scratch, images, grad_images, grad_verts,
-                    grad_light_params, grad_albedo, reps):
+                    grad_light_params, grad_albedo, reps, flush=None):
         """Mean duration (ms) of every pipeline stage over `reps` eager
-        forward + backward passes on `stream`, timed with HIP events."""
+        forward + backward passes on `stream`, timed with HIP events.  With
+        `flush` (a device tensor, e.g. 1 GiB), the library overwrites it
+        before every stage so that each stage starts with cold caches."""
         ms = (C.c_float * len(STAGES))()
         with torch.cuda.stream(stream):
             _lib.call('dsm_time_stages', self.handle, _ptr(verts), _ptr(light_params), _ptr(albedo), _ptr(saved),
                       saved.numel(), _ptr(scratch), scratch.numel(), _ptr(images), _ptr(grad_images),
-                      _ptr(grad_verts), _ptr(grad_light_params), _ptr(grad_albedo), int(reps), ms,
+                      _ptr(grad_verts), _ptr(grad_light_params), _ptr(grad_albedo), int(reps),
+                      _ptr(flush), 0 if flush is None else flush.numel() * flush.element_size(), ms,
                       C.c_void_p(stream.cuda_stream))
         return dict(zip(STAGES, (float(x) for x in ms)))
 
