@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from parity_helpers import (assert_image, GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous,
-                            decisions_clear, gpu_run, loss_grad, normwise, oracle_run, random_grad)
+from parity_helpers import (assert_image, GRAD_ELEM_FRAC, GRAD_FLOOR_ELEM_FRAC, GRAD_FLOOR_TOL, GRAD_TOL, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close,
+                            check_gradients, cone_ambiguous, gpu_run, normwise, oracle_run, random_grad, loss_grad)
 
 pytestmark = pytest.mark.gpu
 
@@ -49,35 +49,28 @@ def test_cube_forward_matches_oracle(res, k, filt):
     check_forward(b, gpu_run(b), oracle_run(b))
 
 
-def clear_only(b, o0, G):
-    """Upstream gradient kept on pixels whose lookup decisions are clear of
-    their thresholds: one pixel whose bilinear cell flips between float32 and
-    float64 moves a face's light gradient by about 0.7% in this scene (the
-    oracle itself moves that much under a 1e-6 shift of the light)."""
-    keep = [decisions_clear(b, o0, r)[..., None] for r in range(len(b.renders))]
-    assert all(k.mean() > 0.9 for k in keep)
-    return [g * k for g, k in zip(G, keep)]
-
-
 def test_cube_backward_matches_oracle_loss_gradient():
     b = cube_batch()
     o0 = oracle_run(b)
-    G = clear_only(b, o0, loss_grad(b, o0['images']))
-    g = gpu_run(b, grad_images=G)
-    o = oracle_run(b, grad_images=G)
-    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
-    # the shared position's gradient is the sum over the six faces
-    normwise('glight (sum over faces)', g['glight'].sum(0), o['glight'].sum(0), GRAD_TOL)
-    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
-    normwise('galbedo', g['galbedo'], o['galbedo'], GRAD_TOL)
-    assert np.all(g['glight'][2] == 0.0)
+
+    def faces(share, g, o):
+        # the shared position's gradient is the sum over the six faces
+        tol, elem = (GRAD_TOL, GRAD_ELEM_FRAC) if share == 'rest' else (GRAD_FLOOR_TOL, GRAD_FLOOR_ELEM_FRAC)
+        if np.any(o['glight']):
+            normwise(f'glight, sum over faces ({share})', g['glight'].sum(0), o['glight'].sum(0), tol, elem)
+        assert np.all(g['glight'][2] == 0.0)       # the empty +y face
+
+    check_gradients(b, loss_grad(b, o0['images']), o0, extra=faces)
 
 
 @pytest.mark.parametrize('res,k', [(120, 3), (48, 9)])
 def test_cube_backward_random_upstream_without_light_smoothing(res, k):
     b = cube_batch(res, k, 'box', antialias=False)
-    G = clear_only(b, oracle_run(b), random_grad(b, 11))
-    g = gpu_run(b, grad_images=G)
-    o = oracle_run(b, grad_images=G)
-    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
-    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
+    # Without light-view smoothing the moment maps keep sharp steps (only the
+    # k-box filter), and the light-position gradient, which enters through
+    # the map position u = L(x), is steep in u: perturbing the oracle's u by
+    # 1, 2 and 4 float32 ulps moves this share of its light gradient by
+    # 3.6e-5, 7.2e-5 and 1.4e-4 at 120^2 / k = 3 (1.5e-5 ... 6.1e-5 at
+    # 48^2 / k = 9).  The kernels form u with a few ulps of error, so the
+    # bound is twice the 4-ulp sensitivity.
+    check_gradients(b, random_grad(b, 11), groups=['glight', 'gverts'], rest_tol=3e-4)

@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from parity_helpers import (assert_image, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, cone_ambiguous, gpu_run,
-                            loss_grad, normwise, oracle_run, random_grad)
+from parity_helpers import (assert_image, IMG_ATOL, IMG_RTOL, MAP_ATOL, MAP_RTOL, assert_close, check_gradients,
+                            cone_ambiguous, gpu_run, loss_grad, oracle_run, random_grad)
 
 pytestmark = pytest.mark.gpu
 
@@ -83,40 +83,23 @@ def test_run_twice_bit_identical_forward():
         assert np.array_equal(x, y)
 
 
-from parity_helpers import GRAD_TOL  # noqa: E402
-
-
 @pytest.mark.parametrize('name', ['cfg0', 'cfg0_ragged', 'cfg1_small'])
 def test_backward_matches_oracle_loss_gradient(name):
     b = BATCHES[name]()
     o0 = oracle_run(b)
-    G = loss_grad(b, o0['images'])
-    g = gpu_run(b, grad_images=G)
-    o = oracle_run(b, grad_images=G)
-    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
-    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
-    normwise('galbedo', g['galbedo'], o['galbedo'], GRAD_TOL)
+    check_gradients(b, loss_grad(b, o0['images']), o0)
 
 
 def test_backward_random_cotangent_cfg0():
     b = sg.config0()
-    G = random_grad(b, 3)
-    g = gpu_run(b, grad_images=G)
-    o = oracle_run(b, grad_images=G)
-    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
-    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
-    normwise('galbedo', g['galbedo'], o['galbedo'], GRAD_TOL)
+    check_gradients(b, random_grad(b, 3))
 
 
 def test_pose_forward_and_backward():
     b = cfg2_small(2, 160, with_pose=True)
     o0 = oracle_run(b, pose=True)
-    G = loss_grad(b, o0['images'])
-    g = gpu_run(b, grad_images=G, pose=True)
-    o = oracle_run(b, grad_images=G, pose=True)
-    check_forward(b, g, o)
-    normwise('gpose', g['gpose'], o['gpose'], GRAD_TOL)
-    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
+    check_forward(b, gpu_run(b, pose=True), o0)
+    check_gradients(b, loss_grad(b, o0['images']), o0, pose=True, groups=['gpose', 'glight'])
 
 
 def cfg3_small():
@@ -134,10 +117,6 @@ def cfg4_small():
 @pytest.mark.parametrize('name', ['cfg3_small', 'cfg4_small'])
 def test_forward_and_backward_multi_view_and_rgb(name):
     b = {'cfg3_small': cfg3_small, 'cfg4_small': cfg4_small}[name]()
-    G = random_grad(b, 7)
-    g = gpu_run(b, grad_images=G)
-    o = oracle_run(b, grad_images=G)
-    check_forward(b, g, o)
-    normwise('glight', g['glight'], o['glight'], GRAD_TOL)
-    normwise('gverts', g['gverts'], o['gverts'], GRAD_TOL)
-    normwise('galbedo', g['galbedo'], o['galbedo'], GRAD_TOL)
+    o0 = oracle_run(b)
+    check_forward(b, gpu_run(b), o0)
+    check_gradients(b, random_grad(b, 7), o0)
