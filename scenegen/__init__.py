@@ -442,22 +442,28 @@ def grid_quad(half: float, y: float, n: int):
 
 
 def minimal_plane(k: int = 5, antialias: bool = True, filter: str = 'box', resolution: int = 256,
-                  view: int = 128, occluder_tess: int = 1, offset=(0.0, 0.0, 0.0)) -> Batch:
+                  view: int = 128, occluder_tess: int = 1, offset=(0.0, 0.0, 0.0), rotation=(0.0, 0.0, 0.0),
+                  camera_height: float = 0.45) -> Batch:
     """The "minimal plane" setup of the convergence experiments (supplementary,
     experiment details): a square occluder (half-size 0.25 at y = 0.5) over a
     parallel square receiver (half-size 0.75 at y = 0), a directional light
     travelling straight down, and a camera between the two looking down at
     the receiver, so that the images show only the shadow.  The occluder's
-    vertices come first and follow the scene pose (translation `offset`
-    relative to the reference, which is pose zero)."""
+    vertices come first and follow the scene pose: rotation `rotation`
+    (axis-angle, about the occluder's centre) and translation `offset`
+    relative to the reference, which is pose zero.  The occluder is an
+    occluder_tess x occluder_tess grid of quads (2 occluder_tess^2
+    triangles).  The camera sits at `camera_height` above the receiver's
+    centre (below a slanted occluder's lowest point for the resolution
+    experiment)."""
     ov, of = grid_quad(0.25, 0.0, occluder_tess)     # object space, centre (0, 0.5, 0)
     rv, rf = quad(0.75, 0.0)
     v, f = merge([(ov, of), (rv, rf)])
     sc = Scene(verts=v, faces=f, albedo=np.full((len(f), 1), 0.8, np.float32), pose_count=len(ov),
-               pose_center=f32([0, 0.5, 0]), pose=f32([0, 0, 0, *offset]))
+               pose_center=f32([0, 0.5, 0]), pose=f32([*rotation, *offset]))
     light = Light('directional', f32([0, -1, 0]), resolution=resolution, filter=filter, k=k,
                   up=f32([0, 0, 1]), ortho_half=1.0, antialias=antialias)
-    cam = Camera(eye=f32([0, 0.45, 0]), target=f32([0, 0, 0]), fov_deg=120.0, width=view, height=view,
+    cam = Camera(eye=f32([0, camera_height, 0]), target=f32([0, 0, 0]), fov_deg=120.0, width=view, height=view,
                  up=f32([0, 0, -1]))
     return Batch('minimal-plane', [sc], [light], [cam], [Render(0, [0])], channels=1,
                  target_poses=[np.zeros(6, np.float32)])

@@ -1,7 +1,18 @@
-"""Shadow gradients need the light-view edge smoothing: on the minimal-plane
-scene a displaced occluder corner is recovered with it and stays put without
-it, for any filter size; a displaced occluder is recovered with Adam."""
+"""The minimal-plane experiments (Sec. 5; supplementary B): shadow gradients
+need the light-view edge smoothing (a displaced occluder corner is recovered
+with it and stays put without it, for any filter size; a displaced occluder
+is recovered with Adam); the visibility Jacobian of a translated occluder
+matches the oracle's, turns sparse for a finely tessellated occluder and is
+spread by the filter; low map resolution misses a steeply slanted occluder.
+The scene itself is compared with the oracle, its culled occluder included."""
+import numpy as np
 import pytest
+import torch
+
+from oracle import pipeline as P
+from parity_helpers import (AMBIGUOUS_MAX, GRAD_ELEM_FRAC, GRAD_FLOOR_ELEM_FRAC, MAP_ATOL, MAP_RTOL, assert_close,
+                            assert_image, check_gradients, decisions_clear, floor_conditioned, gpu_run, oracle_run,
+                            random_grad)
 
 pytestmark = pytest.mark.gpu
 
@@ -23,3 +34,91 @@ def test_translation_recovered():
     e = r['signed_error']
     print('signed error', e[0], e[50], e[-1], flush=True)
     assert abs(e[-1]) < 0.2 * abs(e[0])
+
+
+def _rotated(tess=4, k=5, resolution=128, view=64, rot_deg=15.0):
+    import scenegen as sg
+    return sg.minimal_plane(k=k, resolution=resolution, view=view, occluder_tess=tess,
+                            rotation=(0.0, float(np.deg2rad(rot_deg)), 0.0))
+
+
+def test_minimal_plane_matches_oracle():
+    """The scene of these experiments against the oracle: the occluder sits
+    behind the camera, so every one of its triangles is culled in the camera
+    view (and counted), while it shadows the receiver through the light view."""
+    b = _rotated()
+    g = gpu_run(b, pose=True)
+    o = oracle_run(b, pose=True)
+    for v, (kg, ko) in enumerate(zip(g['keys'], o['keys'])):
+        assert np.array_equal(kg, ko), f'view {v}: keys differ'
+    assert_close('M', g['M'][0], o['M'][0], MAP_RTOL, MAP_ATOL)
+    assert_image('image', g['images'][0], o['images'][0], b, o, 0, smoothed=True)
+    culled = o['culled'] + sum(v['rv']['st']['culled'] for v in o['raw']['views'])
+    n_occ = 2 * 4 * 4
+    assert culled == n_occ and g['stats']['culled'] == culled
+    check_gradients(b, random_grad(b, 2), o, pose=True, groups=['gpose', 'glight'])
+
+
+def _oracle_jacobian(b):
+    """d(image)/d(translation x) of every pixel from the oracle: forward-over-
+    reverse (the gradient for a symbolic upstream u, differentiated in u)."""
+    base, poses, lp, alb = P.scene_leaves(b, requires_grad=True)
+    out = P.render(b, P.world_vertices(b, base, poses), lp, alb)
+    img = out['images'][0]
+    u = torch.ones_like(img, requires_grad=True)
+    g = torch.autograd.grad(img, poses[0], grad_outputs=u, create_graph=True)[0][3]
+    return torch.autograd.grad(g, u)[0].detach().numpy()[..., 0]
+
+
+@pytest.mark.parametrize('k', [1, 5])
+def test_jacobian_matches_oracle(k):
+    """The per-pixel Jacobian of the reverse passes (one per pixel) equals the
+    oracle's forward-over-reverse Jacobian, on pixels whose lookup decisions
+    are clear (elementwise against the largest entry; floor-conditioned
+    pixels at the floor bound)."""
+    from paper_2308_10896_amd import minimal_plane as mp
+    b = _rotated(tess=8, k=k, resolution=64, view=32)
+    jac, _ = mp.jacobian_image(8, k, resolution=64, view=32, rot_deg=15.0)
+    o = oracle_run(b, pose=True)
+    want = _oracle_jacobian(b)
+    clear = decisions_clear(b, o, 0)
+    cond = floor_conditioned(b, o, 0, dilate=1)
+    scale = np.abs(want).max()
+    err = np.abs(jac - want) / scale
+    print(f'k {k}: max|J| {scale:.3f}, error {err[clear & ~cond].max():.2e} (floor-conditioned '
+          f'{err[clear & cond].max() if (clear & cond).any() else 0.0:.2e}), {int((~clear).sum())} pixels ambiguous')
+    assert err[clear & ~cond].max() <= GRAD_ELEM_FRAC
+    if (clear & cond).any():
+        assert err[clear & cond].max() <= GRAD_FLOOR_ELEM_FRAC
+    assert (~clear).mean() <= AMBIGUOUS_MAX
+
+
+def test_jacobian_sparse_for_fine_tessellation():
+    """A 130,050-triangle occluder leaves most of the shadow outline without
+    a derivative at k = 1 (smoothing acts only where the front triangle exits
+    through a silhouette edge); two triangles do not; a wider filter spreads
+    the sparse derivative back over the outline."""
+    from paper_2308_10896_amd import minimal_plane as mp
+    rows = {(r['occluder_triangles'], r['k']): r for r in
+            mp.jacobian_experiment(tess_list=(1, 255), ks=(1, 9), resolution=256, view=64)}
+    for key, r in rows.items():
+        print(key, r, flush=True)
+    coarse, fine, fine9 = rows[(2, 1)], rows[(130050, 1)], rows[(130050, 9)]
+    assert fine['outline_coverage'] < 0.5 * coarse['outline_coverage']
+    assert fine9['outline_coverage'] > 2.0 * fine['outline_coverage']
+
+
+def test_low_resolution_misses_slanted_occluder():
+    """A plane tilted to 88 degrees casts a strip 0.017 wide: a 32^2 map
+    (texels 0.0625 wide) misses it, a 1024^2 map captures it; the shadow
+    border widens with the filter size."""
+    from paper_2308_10896_amd import minimal_plane as mp
+    rows = {r['resolution']: r for r in mp.resolution_experiment(slants_deg=(88.0,), resolutions=(32, 1024))}
+    print(rows, flush=True)
+    assert rows[32]['ratio'] < 0.1
+    assert rows[1024]['ratio'] > 0.6
+    flat = mp.resolution_experiment(slants_deg=(0.0,), resolutions=(256,))[0]
+    assert abs(flat['ratio'] - 1.0) < 0.05
+    widths = [r['border_width'] for r in mp.filter_width_experiment(ks=(1, 9, 25))]
+    print('border widths', widths, flush=True)
+    assert widths[0] < widths[1] < widths[2]
