@@ -75,25 +75,32 @@ def parse():
     ap.add_argument('--res', type=int, default=512)
     ap.add_argument('--no-plain', action='store_true')
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--cpu-seconds', type=float, default=15.0,
-                    help='time budget of the oracle baseline sample')
+    ap.add_argument('--cpu-seconds', type=float, default=24.0,
+                    help='time budget of the oracle baseline (three passes over one sample)')
     ap.add_argument('--stage-reps', type=int, default=10)
     ap.add_argument('--tile', type=int, default=0, help='raster tile side; 0: autotune')
     ap.add_argument('--no-other', action='store_true', help='skip the other configurations')
+    ap.add_argument('--no-cold', action='store_true', help='skip the cold-cache stage timing')
     return ap.parse_args()
 
 
-def timed(fn, steps, stream):
+def timed(fn, steps, stream, per_step=None):
+    """Seconds for `steps` calls of fn, bracketed by synchronizations and HIP
+    events on `stream`; with a list `per_step`, each step's milliseconds
+    (events recorded between the steps) are appended to it."""
     import torch
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1 if per_step is not None else 2)]
+    ev[0].record(stream)
+    for i in range(steps):
         fn()
-    e1.record(stream)
+        if per_step is not None:
+            ev[i + 1].record(stream)
+    ev[-1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1000.0
+    if per_step is not None:
+        per_step.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    return ev[0].elapsed_time(ev[-1]) / 1000.0
 
 
 def main():
@@ -144,7 +151,8 @@ def main():
     for _ in range(args.warmup):
         step_batched()
     torch.cuda.synchronize()
-    t_batched = timed(step_batched, args.steps, stream)
+    step_ms = []
+    t_batched = timed(step_batched, args.steps, stream, step_ms)
     R = len(batch.renders)
     batched_rps = R * args.steps / t_batched
     st = plan.stats(saved)
@@ -202,6 +210,7 @@ def main():
         'steps': args.steps,
         'warmup': args.warmup,
         'ms_per_step': round(1000 * t_batched / args.steps, 4),
+        'ms_per_step_p10_p50_p90': [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],
         'higher_is_better': True,
         'scaling': 'weak',
         'vs_baseline': None,
@@ -219,6 +228,7 @@ def main():
             'bin_capacity_scale': int(plan.info.bin_capacity_scale),
             'autotune': tune,
             'stages_us': kern['stages_us'],
+            'stages_us_cold': kern['stages_us_cold'],
             'other_configs': other,
         },
         'roofline': kern['roofline'],
@@ -249,6 +259,13 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
     from paper_2308_10896_amd import dsm
     stages = plan.time_stages(stream, verts, lp, alb, saved, scratch, images, gimg, gverts, glp, galb,
                               args.stage_reps)
+    # the same with the caches (the 256 MB MALL included) evicted before every stage
+    stages_cold = None
+    if not args.no_cold:
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=verts.device)
+        stages_cold = plan.time_stages(stream, verts, lp, alb, saved, scratch, images, gimg, gverts, glp, galb,
+                                       args.stage_reps, flush=flush)
+        del flush
     n, S = len(plan.light_res), plan.light_res[0]
     P = args.res * args.res
     C = 1
@@ -267,8 +284,13 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
         us = 1000.0 * stages[name]
         tr = pmc_traffic(name, tile)
         kernels[name] = dict(us=round(us, 2), bytes=b, gbs=round(b / (us * 1e-6) / 1e9, 1),
-                             frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                             traffic=None if tr is None else round(tr))
+                             frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+        if stages_cold is not None:
+            us_cold = 1000.0 * stages_cold[name]
+            kernels[name].update(us_cold=round(us_cold, 2), gbs_cold=round(b / (us_cold * 1e-6) / 1e9, 1),
+                                 frac_cold=round(b / (us_cold * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+        kernels[name].update(traffic=None if tr is None else round(tr),
+                             traffic_gbs=None if tr is None else round(tr / (us * 1e-6) / 1e9, 1))
     reps = 20
     with torch.cuda.stream(stream):
         maps = torch.stack([plan.light_maps(saved, scratch, l, 1) for l in range(n)]).contiguous()
@@ -290,7 +312,9 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
             'frac': d['frac'], 'traffic': d['traffic'],
             'kernels': kernels,
             'copy_gbs': round(copy_gbs, 1)}
-    return {'stages_us': {k: round(1000.0 * v, 2) for k, v in stages.items()}, 'roofline': roof}
+    return {'stages_us': {k: round(1000.0 * v, 2) for k, v in stages.items()},
+            'stages_us_cold': None if stages_cold is None else {k: round(1000.0 * v, 2) for k, v in stages_cold.items()},
+            'roofline': roof}
 
 
 def other_configs(stream, steps=10, warmup=3):
@@ -331,35 +355,76 @@ def other_configs(stream, steps=10, warmup=3):
     return res
 
 
+def host_cpu():
+    """Model name and logical-CPU counts of this host."""
+    model = None
+    try:
+        with open('/proc/cpuinfo') as f:
+            for line in f:
+                if line.startswith('model name'):
+                    model = line.split(':', 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {'model': model, 'nproc': os.cpu_count(), 'affinity': len(os.sched_getaffinity(0))}
+
+
+def _oracle_fwd_bwd(b1):
+    from oracle import pipeline as P
+    base, poses, lp, alb = P.scene_leaves(b1)
+    out = P.render(b1, P.world_vertices(b1, base, poses), lp, alb)
+    loss = sum((im ** 2).sum() for im in out['images'])
+    loss.backward()
+
+
 def cpu_baseline(batch, budget_s):
     """The oracle (float64, plain numpy/torch) timed on this host's cores:
     fwd+bwd of the batch's scenes, smallest first and then in a seeded
-    order, until `budget_s` seconds have passed."""
+    order, until about a third of `budget_s` has passed; that sample is then
+    timed twice more and the median of the three passes is reported.  The
+    tiny-cube and icosphere workloads are timed beside it (median of 3).
+    Torch keeps the thread count the environment gives it (OMP_NUM_THREADS,
+    the host threads allotted to one GPU)."""
     import torch
     import scenegen as sg
-    from oracle import pipeline as P
     threads = torch.get_num_threads()
     tris = np.array([len(s.faces) for s in batch.scenes])
     first = int(np.argmin(tris))
     rest = [int(i) for i in np.random.default_rng(1).permutation(len(tris)) if int(i) != first]
-    done = []
-    t0 = time.time()
+
+    def single(i):
+        return sg.Batch(batch.name, [batch.scenes[i]], [sg.Light(**{**batch.lights[i].__dict__, 'scene': 0})],
+                        [sg.Camera(**{**batch.cameras[i].__dict__, 'scene': 0})], [sg.Render(0, [0])], channels=1,
+                        target_poses=[np.zeros(6, np.float32)])
+
+    done, t0 = [], time.time()
     for i in [first] + rest:
-        b1 = sg.Batch(batch.name, [batch.scenes[i]], [sg.Light(**{**batch.lights[i].__dict__, 'scene': 0})],
-                      [sg.Camera(**{**batch.cameras[i].__dict__, 'scene': 0})], [sg.Render(0, [0])], channels=1,
-                      target_poses=[np.zeros(6, np.float32)])
-        base, poses, lp, alb = P.scene_leaves(b1)
-        out = P.render(b1, P.world_vertices(b1, base, poses), lp, alb)
-        loss = sum((im ** 2).sum() for im in out['images'])
-        loss.backward()
+        _oracle_fwd_bwd(single(i))
         done.append(i)
-        if time.time() - t0 >= budget_s:
+        if time.time() - t0 >= budget_s / 3.0:
             break
-    dt = time.time() - t0
+    passes = [time.time() - t0]
+    for _ in range(2):
+        t0 = time.time()
+        for i in done:
+            _oracle_fwd_bwd(single(i))
+        passes.append(time.time() - t0)
+    dt = float(np.median(passes))
+    other = {}
+    for name, make in (('tiny cube, 256^2', sg.config0), ('icosphere, spot, 512^2', sg.config1)):
+        b1 = make()
+        ts = []
+        for _ in range(3):
+            t0 = time.time()
+            _oracle_fwd_bwd(b1)
+            ts.append(time.time() - t0)
+        other[name] = {'renders_per_s': round(1.0 / float(np.median(ts)), 4), 'seconds': [round(t, 3) for t in ts]}
     return {'value': round(len(done) / dt, 4), 'unit': 'renders/s', 'cores': int(threads),
-            'kind': 'oracle',
+            'kind': 'oracle', 'host': host_cpu(),
             'sample': f'{len(done)} of the {len(batch.scenes)} scenes (smallest first, then seeded order; '
-                      f'{int(tris[done].sum())} triangles in all), fwd+bwd each in float64, {dt:.1f} s'}
+                      f'{int(tris[done].sum())} triangles in all), fwd+bwd each in float64; median of 3 passes '
+                      f'({", ".join(f"{t:.1f}" for t in passes)} s)',
+            'other_configs': other}
 
 
 if __name__ == '__main__':
