@@ -84,6 +84,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result stays alone on stdout)."""
+    print(f'[bench] {msg}', file=sys.stderr, flush=True)
+
+
 def timed(fn, steps, stream, per_step=None):
     """Seconds for `steps` calls of fn, bracketed by synchronizations and HIP
     events on `stream`; with a list `per_step`, each step's milliseconds
@@ -129,6 +134,7 @@ def main():
             posed = plan.pose_forward(local, poses)
             tile, scale, tune_ms = dsm.autotune(batch, posed, lp, alb, gimg, reps=3, stream=stream)
         tune = {'tile': tile, 'bin_capacity_scale': scale, 'ms_fwd_bwd': round(tune_ms, 4)}
+        progress(f'autotuned: tile {tile}, bin scale {scale}')
     else:
         tile, scale = args.tile, 0
     del plan
@@ -155,12 +161,14 @@ def main():
     t_batched = timed(step_batched, args.steps, stream, step_ms)
     R = len(batch.renders)
     batched_rps = R * args.steps / t_batched
+    progress(f'batched: {batched_rps:.1f} renders/s')
     st = plan.stats(saved)
     assert st['culled'] == 0 and st['bad_indices'] == 0, st
 
     # ---------------- dominant kernels, timed live with HIP events on the plan's stream
     kern = kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, gimg, gverts, glp, galb,
                           args)
+    progress('stage timings done')
 
     # ---------------- plain: one plan per scene, eager calls, no graph
     plain_rps = None
@@ -191,16 +199,19 @@ def main():
         psteps = max(2, args.steps // 4)
         t_plain = timed(step_plain, psteps, stream)
         plain_rps = R * psteps / t_plain
+        progress(f'plain: {plain_rps:.1f} renders/s')
 
     # ---------------- the other configurations of the method, absolute rates
     other = None
     if not args.no_other:
         other = other_configs(stream)
+        progress('other configurations done')
 
     # ---------------- CPU baseline: the oracle on a bounded sample of scenes
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, args.cpu_seconds)
+        progress(f"oracle baseline: {cpu['value']} renders/s")
 
     out = {
         'metric': METRIC,
@@ -348,6 +359,7 @@ def other_configs(stream, steps=10, warmup=3):
             plan.graph_launch(stream)
         t = timed(lambda: plan.graph_launch(stream), steps, stream)
         R = len(batch.renders)
+        progress(f'{name}: {R * steps / t:.1f} renders/s')
         res[name] = {'renders_per_s': round(R * steps / t, 2), 'ms_per_step': round(1000 * t / steps, 4),
                      'renders_per_step': R, 'triangles': int(sum(len(sc.faces) for sc in batch.scenes))}
         del plan, saved, scratch

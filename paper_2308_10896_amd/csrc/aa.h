@@ -60,6 +60,10 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     const unsigned sm = silm[v.setup_off + t];
     if (sm == 0) return false;                       // no silhouette edge to cross
     const TriSetup &S = setup[v.setup_off + t];
+    // the triangle's three vertex indices, loaded with its setup record so
+    // that the vertex fetch below is the only load that waits on the edge choice
+    const size_t fidx = (size_t)(v.face_off + (int)t);
+    const int fv[3] = {faces[3 * fidx], faces[3 * fidx + 1], faces[3 * fidx + 2]};
     const int fX = fi * kSub + kSub / 2, fY = fj * kSub + kSub / 2;
     const int oX = oi * kSub + kSub / 2, oY = oj * kSub + kSub / 2;
     float best = 0.f;
@@ -82,9 +86,8 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
     if (!((sm >> ebest) & 1)) return false;
     const bool sw = S.swapped != 0;
     const int oa = orig_slot(a, sw), ob = orig_slot(b, sw);
-    const size_t fidx = (size_t)(v.face_off + (int)t);
-    out.va = faces[3 * fidx + oa];
-    out.vb = faces[3 * fidx + ob];
+    out.va = oa == 0 ? fv[0] : oa == 1 ? fv[1] : fv[2];
+    out.vb = ob == 0 ? fv[0] : ob == 1 ? fv[1] : fv[2];
     double ca[4], cb[4];
     clip_f64(v.M, verts + 3 * (size_t)(v.vert_off + out.va), ca);
     clip_f64(v.M, verts + 3 * (size_t)(v.vert_off + out.vb), cb);

@@ -104,11 +104,12 @@ __device__ __forceinline__ void bary_backward(const BaryFull &b, float px, float
 
 // ----------------------------------------------------------------------------- camera smoothing^T
 
+template <int C>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void aa_camera_backward_kernel(
     const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders, const TriSetup *__restrict__ setup,
     const int *__restrict__ faces, const unsigned char *__restrict__ silm, const float *__restrict__ verts,
     const unsigned long long *__restrict__ keys, const float *__restrict__ img0, const float *__restrict__ gimg,
-    float *__restrict__ gimg0, float4 *__restrict__ gclip, int C) {
+    float *__restrict__ gimg0, float4 *__restrict__ gclip) {
     const Blk blk = xcd_block2();
     const RenderConst &R = renders[blk.y];
     const ViewConst &v = views[R.camera_view];
@@ -117,18 +118,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void a
     if (p >= W * H) return;
     const float *c0 = img0 + R.img_off;
     const float *g = gimg + R.img_off;
-    float acc[3];
-    for (int c = 0; c < C; ++c) acc[c] = g[(long long)p * C + c];
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) acc[c] = g[(long long)p * C + c];
+    const float gself[3] = {acc[0], acc[1], acc[2]};
     if (v.antialias && v.nfaces > 0) {
         const int i = p % W, j = p / W;
         const unsigned long long *kv = keys + v.pix_off;
         const unsigned long long ks = kv[p];
         const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
         const AANeighbours nb = aa_neighbours(v, kv, silm, ks, i, j);
+        // image values and upstream gradients of this sample and the
+        // candidate neighbours, fetched before the pair tests so that they
+        // arrive with the triangle records
+        const bool any = nb.cand[0] || nb.cand[1] || nb.cand[2] || nb.cand[3];
+        float cself[3], cn[4][3], gn[4][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cself[c] = (any && c < C) ? c0[(long long)p * C + c] : 0.f;
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const bool ld = nb.cand[d] && c < C;
+                cn[d][c] = ld ? c0[(long long)nb.q[d] * C + c] : 0.f;
+                gn[d][c] = ld ? g[(long long)nb.q[d] * C + c] : 0.f;
+            }
+#pragma unroll
         for (int d = 0; d < 4; ++d) {
             if (!nb.cand[d]) continue;
             const int in_ = i + di[d], jn = j + dj[d];
-            const int q = nb.q[d];
             const unsigned long long kn = nb.kn[d];
             bool self_front;
             AAPair pr;
@@ -136,10 +155,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void a
             const bool self_recv = (pr.recv == 1) != self_front;
             if (self_recv) {
                 double galpha = 0;
-                for (int c = 0; c < C; ++c) {
-                    const float gs = g[(long long)p * C + c];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (c >= C) continue;
+                    const float gs = gself[c];
                     acc[c] -= pr.w * gs;
-                    galpha += (double)gs * (c0[(long long)q * C + c] - c0[(long long)p * C + c]);
+                    galpha += (double)gs * (cn[d][c] - cself[c]);
                 }
                 galpha *= pr.recv == 1 ? 1.0 : -1.0;      // w = alpha - 1/2 or 1/2 - alpha
                 float4 *ga = gclip + v.clip_off + pr.va;
@@ -151,11 +172,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void a
                 atomic_add_f32(&gb->y, (float)(galpha * pr.dby));
                 atomic_add_f32(&gb->w, (float)(galpha * pr.dbw));
             } else {
-                for (int c = 0; c < C; ++c) acc[c] += pr.w * g[(long long)q * C + c];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (c < C) acc[c] += pr.w * gn[d][c];
             }
         }
     }
-    for (int c = 0; c < C; ++c) gimg0[R.img_off + (long long)p * C + c] = acc[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) gimg0[R.img_off + (long long)p * C + c] = acc[c];
 }
 
 // ----------------------------------------------------------------------------- reduction by (triangle, tile)
@@ -1292,8 +1317,13 @@ hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *
                                      const unsigned long long *keys, const float *img0, const float *gimg,
                                      float *gimg0, float4 *gclip, int C, hipStream_t s) {
     if (R == 0) return hipSuccess;
-    hipLaunchKernelGGL(aa_camera_backward_kernel, dim3((max_pix + 255) / 256, R), dim3(256), 0, s, views, renders,
-                       setup, faces, silm, verts, keys, img0, gimg, gimg0, gclip, C);
+    const dim3 grid((max_pix + 255) / 256, R);
+    if (C == 1)
+        hipLaunchKernelGGL(aa_camera_backward_kernel<1>, grid, dim3(256), 0, s, views, renders, setup, faces, silm,
+                           verts, keys, img0, gimg, gimg0, gclip);
+    else
+        hipLaunchKernelGGL(aa_camera_backward_kernel<3>, grid, dim3(256), 0, s, views, renders, setup, faces, silm,
+                           verts, keys, img0, gimg, gimg0, gclip);
     return hipGetLastError();
 }
 

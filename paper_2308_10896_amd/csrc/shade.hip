@@ -21,6 +21,9 @@
 
 namespace dsm {
 
+// Pixels per thread of the lookup (latency hiding; see lookup_kernel).
+constexpr int kLookupPixelsPerThread = 2;
+
 struct Bary {
     float b0, b1, b2;
 };
@@ -98,12 +101,13 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVer
 
 // Light maps: planar 2-channel; grid.y = light view.  Camera images:
 // interleaved C channels; grid.y = render (view = that render's camera).
-template <bool LIGHT>
+// C is a template parameter so that the per-channel values stay in registers.
+template <bool LIGHT, int C>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void aa_forward_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
                                   const TriSetup *__restrict__ setup, const int *__restrict__ faces,
                                   const unsigned char *__restrict__ silm, const float *__restrict__ verts,
                                   const unsigned long long *__restrict__ keys, const float *__restrict__ src,
-                                  float *__restrict__ dst, int C) {
+                                  float *__restrict__ dst) {
     const Blk blk = xcd_block2();
     const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
     const int W = v.W, H = v.H;
@@ -115,147 +119,190 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
     const int i = p % W, j = p / W;
     const unsigned long long *kv = keys + v.pix_off;
     const unsigned long long ks = kv[p];
-    float acc[3];
-    for (int c = 0; c < C; ++c) acc[c] = src[base + (long long)p * pstride + c * cstride];
-    const float self[3] = {acc[0], C > 1 ? acc[1] : 0.f, C > 2 ? acc[2] : 0.f};
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) acc[c] = src[base + (long long)p * pstride + c * cstride];
+    const float self[3] = {acc[0], acc[1], acc[2]};
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
     if (v.antialias && v.nfaces > 0) {
         const AANeighbours nb = aa_neighbours(v, kv, silm, ks, i, j);
+        // values of the candidate neighbours, fetched before the pair tests
+        // so that they arrive with the triangle records
+        float nv[4][3];
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                nv[d][c] = (nb.cand[d] && c < C) ? src[base + (long long)nb.q[d] * pstride + c * cstride] : 0.f;
+#pragma unroll
         for (int d = 0; d < 4; ++d) {
             if (!nb.cand[d]) continue;
             const int in_ = i + di[d], jn = j + dj[d];
-            const int q = nb.q[d];
             const unsigned long long kn = nb.kn[d];
             bool self_front;
             AAPair pr;
             if (!aa_eval<false>(v, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
             const bool self_recv = (pr.recv == 1) != self_front;   // receiver: other when recv==1
             if (!self_recv) continue;
-            for (int c = 0; c < C; ++c) {
-                const float nv = src[base + (long long)q * pstride + c * cstride];
-                acc[c] += pr.w * (nv - self[c]);
-            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (c < C) acc[c] += pr.w * (nv[d][c] - self[c]);
         }
     }
-    for (int c = 0; c < C; ++c) dst[base + (long long)p * pstride + c * cstride] = acc[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) dst[base + (long long)p * pstride + c * cstride] = acc[c];
 }
 
 // ----------------------------------------------------------------------------- lookup + shade
 
-struct Fetch {
-    float m1, m2;
-    int x0, x1, y0, y1;
-    float fx, fy;
-};
-
-// Bilinear fetch of both moments at (sx, sy) (texel centres at integers) from
-// maps of side S whose texel (0, 0) sits P texels inside the stored side
-// S + 2P (P > 0: cube faces padded from their neighbours), clamp-to-edge.
-__device__ __forceinline__ Fetch bilinear2(const float *__restrict__ maps, long long off, int S, int P, float sx,
-                                           float sy) {
-    Fetch f;
-    const float fx0 = floorf(sx), fy0 = floorf(sy);
-    f.fx = sx - fx0;
-    f.fy = sy - fy0;
-    const int ix = (int)fx0 + P, iy = (int)fy0 + P;
-    S += 2 * P;
-    f.x0 = min(max(ix, 0), S - 1);
-    f.x1 = min(max(ix + 1, 0), S - 1);
-    f.y0 = min(max(iy, 0), S - 1);
-    f.y1 = min(max(iy + 1, 0), S - 1);
-    const float2 *m = (const float2 *)(maps + off);          // (m1, m2) interleaved per texel
-    const long long o00 = (long long)f.y0 * S + f.x0, o01 = (long long)f.y0 * S + f.x1;
-    const long long o10 = (long long)f.y1 * S + f.x0, o11 = (long long)f.y1 * S + f.x1;
-    const float w00 = (1.f - f.fx) * (1.f - f.fy), w01 = f.fx * (1.f - f.fy);
-    const float w10 = (1.f - f.fx) * f.fy, w11 = f.fx * f.fy;
-    const float2 t00 = m[o00], t01 = m[o01], t10 = m[o10], t11 = m[o11];
-    f.m1 = ((w00 * t00.x + w01 * t01.x) + w10 * t10.x) + w11 * t11.x;
-    f.m2 = ((w00 * t00.y + w01 * t01.y) + w10 * t10.y) + w11 * t11.y;
-    return f;
-}
-
-__global__ void lookup_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
-                              const int *__restrict__ render_lights, const TriVerts *__restrict__ tv,
-                              const float *__restrict__ albedo, const unsigned long long *__restrict__ keys,
-                              const float *__restrict__ maps, float *__restrict__ img0, int C) {
+// PPT pixels per thread, PPT * 256 contiguous pixels per workgroup (pixel
+// k of a thread at k * 256 + its lane, so every load stays coalesced).  The
+// three dependent gathers of a pixel (its depth|id key, its triangle's
+// record, its map taps) are issued for all PPT pixels before any of them is
+// used, so a thread waits for three round trips per PPT pixels instead of
+// three per pixel.  Each pixel's arithmetic is the one-pixel form, unchanged.
+template <int PPT>
+__global__ __launch_bounds__(256) void lookup_kernel(const ViewConst *__restrict__ views,
+                                                     const RenderConst *__restrict__ renders,
+                                                     const int *__restrict__ render_lights,
+                                                     const TriVerts *__restrict__ tv, const float *__restrict__ albedo,
+                                                     const unsigned long long *__restrict__ keys,
+                                                     const float *__restrict__ maps, float *__restrict__ img0, int C) {
     const RenderConst &R = renders[blockIdx.y];
     const ViewConst &cv = views[R.camera_view];
-    const int W = cv.W, H = cv.H;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= W * H) return;
-    const unsigned long long key = keys[cv.pix_off + p];
-    float *out = img0 + R.img_off + (long long)p * C;
-    if (key == kBgKey) {
-        for (int c = 0; c < C; ++c) out[c] = 0.f;
-        return;
+    const int W = cv.W, H = cv.H, P = W * H;
+    const int p0 = blockIdx.x * (256 * PPT) + (int)threadIdx.x;
+    if (p0 >= P) return;
+    unsigned long long key[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int p = p0 + 256 * k;
+        key[k] = p < P ? keys[cv.pix_off + p] : kBgKey;
     }
-    const int tri = (int)(unsigned)key;
-    const TriVerts r = tv[cv.face_off + tri];
-    const float v0[3] = {r.a.x, r.a.y, r.a.z}, v1[3] = {r.a.w, r.b.x, r.b.y}, v2[3] = {r.b.z, r.b.w, r.c.x};
-    const int i = p % W, j = p / W;
-    const float px = ndc_centre(i, W), py = -ndc_centre(j, H);
-    const float4 c0 = clip_of(cv.M, v0[0], v0[1], v0[2]), c1 = clip_of(cv.M, v1[0], v1[1], v1[2]),
-                 c2 = clip_of(cv.M, v2[0], v2[1], v2[2]);
-    const Bary b = persp_bary_rcp(c0, c1, c2, px, py);
-    const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
-    const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
-    const float z = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
-    const float e1x = v1[0] - v0[0], e1y = v1[1] - v0[1], e1z = v1[2] - v0[2];
-    const float e2x = v2[0] - v0[0], e2y = v2[1] - v0[1], e2z = v2[2] - v0[2];
-    float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-    const float nn = sqrtf((nx * nx + ny * ny) + nz * nz);
-    const float rn = __builtin_amdgcn_rcpf(nn);
-    nx *= rn;
-    ny *= rn;
-    nz *= rn;
-    float shade = 0.f;
+    TriVerts r[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (key[k] != kBgKey) r[k] = tv[cv.face_off + (int)(unsigned)key[k]];
+    float x[PPT], y[PPT], z[PPT], nx[PPT], ny[PPT], nz[PPT], shade[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        shade[k] = 0.f;
+        x[k] = y[k] = z[k] = nx[k] = ny[k] = nz[k] = 0.f;
+        if (key[k] == kBgKey) continue;
+        const float v0[3] = {r[k].a.x, r[k].a.y, r[k].a.z}, v1[3] = {r[k].a.w, r[k].b.x, r[k].b.y},
+                    v2[3] = {r[k].b.z, r[k].b.w, r[k].c.x};
+        const int p = p0 + 256 * k;
+        const int i = p % W, j = p / W;
+        const float px = ndc_centre(i, W), py = -ndc_centre(j, H);
+        const float4 c0 = clip_of(cv.M, v0[0], v0[1], v0[2]), c1 = clip_of(cv.M, v1[0], v1[1], v1[2]),
+                     c2 = clip_of(cv.M, v2[0], v2[1], v2[2]);
+        const Bary b = persp_bary_rcp(c0, c1, c2, px, py);
+        x[k] = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
+        y[k] = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
+        z[k] = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
+        const float e1x = v1[0] - v0[0], e1y = v1[1] - v0[1], e1z = v1[2] - v0[2];
+        const float e2x = v2[0] - v0[0], e2y = v2[1] - v0[1], e2z = v2[2] - v0[2];
+        float cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
+        const float nn = sqrtf((cx * cx + cy * cy) + cz * cz);
+        const float rn = __builtin_amdgcn_rcpf(nn);
+        nx[k] = cx * rn;
+        ny[k] = cy * rn;
+        nz[k] = cz * rn;
+    }
     for (int q = 0; q < R.light_count; ++q) {
         const ViewConst &l = views[render_lights[R.light_begin + q]];
-        // a cube face lights only the directions it owns: skip the fetch elsewhere
-        if (l.kind == kCubeFace && cube_face_of(x - l.pos[0], y - l.pos[1], z - l.pos[2]) != l.cube_face) continue;
-        const float *M = l.M;
-        const float cx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
-        const float cy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
-        const float cw = ((M[12] * x + M[13] * y) + M[14] * z) + M[15];
-        float vis = 1.f;
-        const float rcw = __builtin_amdgcn_rcpf(cw);
-        const float ux = cx * rcw, uy = cy * rcw;
-        if (cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f) {
-            const int S = l.W;
+        const int S = l.W, Sp = S + 2 * l.fpad;
+        const float2 *mm = (const float2 *)(maps + l.fmap_off);     // (m1, m2) interleaved per texel
+        bool inside[PPT];
+        float fx[PPT], fy[PPT];
+        int o00[PPT], o01[PPT], o10[PPT], o11[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            inside[k] = false;
+            fx[k] = fy[k] = 0.f;
+            o00[k] = o01[k] = o10[k] = o11[k] = 0;
+            if (key[k] == kBgKey) continue;
+            // a cube face lights only the directions it owns: no fetch elsewhere
+            if (l.kind == kCubeFace &&
+                cube_face_of(x[k] - l.pos[0], y[k] - l.pos[1], z[k] - l.pos[2]) != l.cube_face)
+                continue;
+            const float *M = l.M;
+            const float cx = ((M[0] * x[k] + M[1] * y[k]) + M[2] * z[k]) + M[3];
+            const float cy = ((M[4] * x[k] + M[5] * y[k]) + M[6] * z[k]) + M[7];
+            const float cw = ((M[12] * x[k] + M[13] * y[k]) + M[14] * z[k]) + M[15];
+            const float rcw = __builtin_amdgcn_rcpf(cw);
+            const float ux = cx * rcw, uy = cy * rcw;
+            inside[k] = cw > 0.f && fabsf(ux) <= 1.f && fabsf(uy) <= 1.f;
+            if (!inside[k]) continue;
             const float sx = (ux + 1.f) * (0.5f * S) - 0.5f;
             const float sy = (1.f - uy) * (0.5f * S) - 0.5f;
-            const Fetch m = bilinear2(maps, l.fmap_off, S, l.fpad, sx, sy);
-            float zw, floor_v;
-            warp_receiver(l, light_depth(l, x, y, z), zw, floor_v);
-            const float var = fmaxf(m.m2 - m.m1 * m.m1, floor_v);
-            const float dd = zw - m.m1;
-            vis = bleed_reduce(l, (zw <= m.m1) ? 1.f : var / (var + dd * dd));
+            const float fx0 = floorf(sx), fy0 = floorf(sy);
+            fx[k] = sx - fx0;
+            fy[k] = sy - fy0;
+            const int ix = (int)fx0 + l.fpad, iy = (int)fy0 + l.fpad;
+            const int x0 = min(max(ix, 0), Sp - 1), x1 = min(max(ix + 1, 0), Sp - 1);
+            const int y0 = min(max(iy, 0), Sp - 1), y1 = min(max(iy + 1, 0), Sp - 1);
+            o00[k] = y0 * Sp + x0; o01[k] = y0 * Sp + x1;
+            o10[k] = y1 * Sp + x0; o11[k] = y1 * Sp + x1;
         }
-        float ox, oy, oz;
-        if (l.kind == kDirectional) {
-            ox = -l.dir[0];
-            oy = -l.dir[1];
-            oz = -l.dir[2];
-        } else {
-            ox = l.pos[0] - x;
-            oy = l.pos[1] - y;
-            oz = l.pos[2] - z;
-            const float on = sqrtf((ox * ox + oy * oy) + oz * oz);
-            ox /= on;
-            oy /= on;
-            oz /= on;
+        float2 t00[PPT], t01[PPT], t10[PPT], t11[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            // offsets of pixels without a fetch are 0, a texel of this map
+            t00[k] = mm[o00[k]]; t01[k] = mm[o01[k]]; t10[k] = mm[o10[k]]; t11[k] = mm[o11[k]];
         }
-        const float lam = fmaxf((nx * ox + ny * oy) + nz * oz, 0.f);
-        float cone = 1.f;
-        if (l.kind == kSpot) {
-            // cos of the angle between x - p and the axis: (-omega) . axis
-            const float ca = -((ox * l.dir[0] + oy * l.dir[1]) + oz * l.dir[2]);
-            cone = ca >= l.cos_half ? 1.f : 0.f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (key[k] == kBgKey) continue;
+            if (l.kind == kCubeFace &&
+                cube_face_of(x[k] - l.pos[0], y[k] - l.pos[1], z[k] - l.pos[2]) != l.cube_face)
+                continue;
+            float vis = 1.f;
+            if (inside[k]) {
+                const float w00 = (1.f - fx[k]) * (1.f - fy[k]), w01 = fx[k] * (1.f - fy[k]);
+                const float w10 = (1.f - fx[k]) * fy[k], w11 = fx[k] * fy[k];
+                const float m1 = ((w00 * t00[k].x + w01 * t01[k].x) + w10 * t10[k].x) + w11 * t11[k].x;
+                const float m2 = ((w00 * t00[k].y + w01 * t01[k].y) + w10 * t10[k].y) + w11 * t11[k].y;
+                float zw, floor_v;
+                warp_receiver(l, light_depth(l, x[k], y[k], z[k]), zw, floor_v);
+                const float var = fmaxf(m2 - m1 * m1, floor_v);
+                const float dd = zw - m1;
+                vis = bleed_reduce(l, (zw <= m1) ? 1.f : var / (var + dd * dd));
+            }
+            float ox, oy, oz;
+            if (l.kind == kDirectional) {
+                ox = -l.dir[0];
+                oy = -l.dir[1];
+                oz = -l.dir[2];
+            } else {
+                ox = l.pos[0] - x[k];
+                oy = l.pos[1] - y[k];
+                oz = l.pos[2] - z[k];
+                const float on = sqrtf((ox * ox + oy * oy) + oz * oz);
+                ox /= on;
+                oy /= on;
+                oz /= on;
+            }
+            const float lam = fmaxf((nx[k] * ox + ny[k] * oy) + nz[k] * oz, 0.f);
+            float cone = 1.f;
+            if (l.kind == kSpot) {
+                // cos of the angle between x - p and the axis: (-omega) . axis
+                const float ca = -((ox * l.dir[0] + oy * l.dir[1]) + oz * l.dir[2]);
+                cone = ca >= l.cos_half ? 1.f : 0.f;
+            }
+            shade[k] += lam * vis * l.intensity * cone;
         }
-        shade += lam * vis * l.intensity * cone;
     }
-    const float rho[3] = {r.c.y, r.c.z, r.c.w};          // albedo, carried in the face record
-    for (int c = 0; c < C; ++c) out[c] = rho[c] * shade;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int p = p0 + 256 * k;
+        if (p >= P) continue;
+        float *out = img0 + R.img_off + (long long)p * C;
+        const float rho[3] = {r[k].c.y, r[k].c.z, r[k].c.w};    // albedo, carried in the face record
+        for (int c = 0; c < C; ++c) out[c] = key[k] == kBgKey ? 0.f : rho[c] * shade[k];
+    }
 }
 
 // ----------------------------------------------------------------------------- launchers
@@ -273,11 +320,14 @@ hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderCon
     if (n == 0) return hipSuccess;
     const dim3 grid((max_pix + 255) / 256, n);
     if (light)
-        hipLaunchKernelGGL(aa_forward_kernel<true>, grid, dim3(256), 0, s, views, renders, setup, faces, silm, verts,
-                           keys, src, dst, 2);
+        hipLaunchKernelGGL((aa_forward_kernel<true, 2>), grid, dim3(256), 0, s, views, renders, setup, faces, silm,
+                           verts, keys, src, dst);
+    else if (C == 1)
+        hipLaunchKernelGGL((aa_forward_kernel<false, 1>), grid, dim3(256), 0, s, views, renders, setup, faces, silm,
+                           verts, keys, src, dst);
     else
-        hipLaunchKernelGGL(aa_forward_kernel<false>, grid, dim3(256), 0, s, views, renders, setup, faces, silm, verts,
-                           keys, src, dst, C);
+        hipLaunchKernelGGL((aa_forward_kernel<false, 3>), grid, dim3(256), 0, s, views, renders, setup, faces, silm,
+                           verts, keys, src, dst);
     return hipGetLastError();
 }
 
@@ -285,8 +335,9 @@ hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int
                          const int *render_lights, const TriVerts *tv, const float *albedo,
                          const unsigned long long *keys, const float *maps, float *img0, int C, hipStream_t s) {
     if (R == 0) return hipSuccess;
-    hipLaunchKernelGGL(lookup_kernel, dim3((max_pix + 255) / 256, R), dim3(256), 0, s, views, renders, render_lights,
-                       tv, albedo, keys, maps, img0, C);
+    constexpr int PPT = kLookupPixelsPerThread;
+    hipLaunchKernelGGL(lookup_kernel<PPT>, dim3((max_pix + 256 * PPT - 1) / (256 * PPT), R), dim3(256), 0, s, views,
+                       renders, render_lights, tv, albedo, keys, maps, img0, C);
     return hipGetLastError();
 }
 
