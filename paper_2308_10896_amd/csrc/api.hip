@@ -522,7 +522,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_glight = o; o = align_up(o + 4 * 3 * (size_t)kGlightBlocks * (size_t)std::max(L, 1));
     p->sc_gF1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
     p->sc_pair_sums = o; o = align_up(o + 4 * 21 * (size_t)p->capacity);
-    p->sc_gtri = o; o = align_up(o + 4 * 21 * ((size_t)tri + 1));
+    p->sc_gtri = o; o = align_up(o + 4 * 24 * ((size_t)tri + 1));       // three 8-float corner records per triangle
     p->sc_biglist = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_part_light = o; o = align_up(o + 4 * 3 * (size_t)(part_light + 1));
     p->sc_part_gm = o; o = align_up(o + 4 * 3 * (size_t)(part_gm + 1));

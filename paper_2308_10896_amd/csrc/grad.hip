@@ -199,6 +199,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void a
 // terms and the bilinear moment-map scatter use atomics.
 constexpr int kNV = 21;   // per pair: 9 world-position terms, 9 clip (x, y, w) terms, 3 albedo terms
 
+// Per-triangle gradient rows (gtri) hold the same 21 values as three 8-float
+// corner records, [world x y z | clip x y w | albedo term of channel c | 0]
+// for corner c, so that the per-vertex gather reads one aligned 32-byte
+// sector per incident corner.  gtri_slot maps value index i (the pair-row
+// order above) to its place in the row.
+constexpr int kGtriStride = 24;
+__host__ __device__ constexpr int gtri_slot(int i) {
+    return i < 9 ? (i / 3) * 8 + i % 3 : i < 18 ? ((i - 9) / 3) * 8 + 3 + (i - 9) % 3 : (i - 18) * 8 + 6;
+}
+
 template <int T>
 struct TileShape {
     static constexpr int NPIX = T * T;
@@ -208,15 +218,20 @@ struct TileShape {
 };
 
 // Per-workgroup sum of N per-thread values, written to dst[0..N) by threads < N.  Uniform call.
-template <int NW, int N>
-__device__ __forceinline__ void block_sum_store(const float (&val)[N], float *dst) {
+struct IdentitySlot {
+    __device__ int operator()(int i) const { return i; }
+};
+
+// Workgroup sums of N values; value i is stored at dst[slot(i)].
+template <int NW, int N, class Slot = IdentitySlot>
+__device__ __forceinline__ void block_sum_store(const float (&val)[N], float *dst, Slot slot = Slot()) {
     __shared__ float part[NW][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
     const float t = wave_sum_multi(val);      // lane 2i holds the wave's total of value i
     const int i = lane >> 1;
     if (NW == 1) {
-        if ((lane & 1) == 0 && i < N) dst[i] = t;
+        if ((lane & 1) == 0 && i < N) dst[slot(i)] = t;
         return;
     }
     if ((lane & 1) == 0 && i < N) part[w][i] = t;
@@ -225,7 +240,7 @@ __device__ __forceinline__ void block_sum_store(const float (&val)[N], float *ds
         float s = 0.f;
 #pragma unroll
         for (int q = 0; q < NW; ++q) s += part[q][threadIdx.x];
-        dst[threadIdx.x] = s;
+        dst[slot(threadIdx.x)] = s;
     }
 }
 
@@ -379,7 +394,8 @@ __device__ __forceinline__ void overflow_rows(const ViewConst &v, const int (&ke
     for (int k = 0; k < PPT; ++k) {
         const bool a = active[k] && !matched[k];
         if (__ballot(a))
-            scatter_by_key(a, key[k], val[k], [&](int t, int i) { return gtri + (size_t)(v.setup_off + t) * kNV + i; });
+            scatter_by_key(a, key[k], val[k],
+                           [&](int t, int i) { return gtri + (size_t)(v.setup_off + t) * kGtriStride + gtri_slot(i); });
     }
 }
 
@@ -932,15 +948,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
 #pragma unroll
         for (int q = 0; q < 18; ++q) val[k][q] = 0.f;
         float g0 = in ? ga[pp] : 0.f, g1 = in ? gbp[pp] : 0.f;
-        if (in && l.antialias) {
+        if (in && l.antialias && l.nfaces > 0) {
             const float gs0 = g0, gs1 = g1;
             const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+            // the four neighbour keys, then their silhouette bytes, each batch
+            // loaded together; a candidate neighbour's map values and
+            // gradients are requested with its triangle's records
+            const AANeighbours nb = aa_neighbours(l, kv, silm, ks, i, j);
+            const bool any = nb.cand[0] || nb.cand[1] || nb.cand[2] || nb.cand[3];
+            const float fs0 = any ? f0a[pp] : 0.f, fs1 = any ? f0b[pp] : 0.f;
+#pragma unroll
             for (int d = 0; d < 4; ++d) {
+                if (!nb.cand[d]) continue;
+                const int q = nb.q[d];
+                const float fn0 = f0a[q], fn1 = f0b[q], gn0 = ga[q], gn1 = gbp[q];
                 const int in_ = i + di[d], jn = j + dj[d];
-                if (in_ < 0 || in_ >= S || jn < 0 || jn >= S) continue;
-                const int q = jn * S + in_;
-                const unsigned long long kn = kv[q];
-                if ((unsigned)kn == (unsigned)ks) continue;
+                const unsigned long long kn = nb.kn[d];
                 bool self_front;
                 AAPair pr;
                 if (!aa_eval<true>(l, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
@@ -948,7 +971,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
                 if (self_recv) {
                     g0 -= pr.w * gs0;
                     g1 -= pr.w * gs1;
-                    double galpha = (double)gs0 * (f0a[q] - f0a[pp]) + (double)gs1 * (f0b[q] - f0b[pp]);
+                    double galpha = (double)gs0 * (fn0 - fs0) + (double)gs1 * (fn1 - fs1);
                     galpha *= pr.recv == 1 ? 1.0 : -1.0;
                     float4 *gpa = gclip + l.clip_off + pr.va;
                     float4 *gpb = gclip + l.clip_off + pr.vb;
@@ -959,8 +982,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
                     atomic_add_f32(&gpb->y, (float)(galpha * pr.dby));
                     atomic_add_f32(&gpb->w, (float)(galpha * pr.dbw));
                 } else {
-                    g0 += pr.w * ga[q];
-                    g1 += pr.w * gbp[q];
+                    g0 += pr.w * gn0;
+                    g1 += pr.w * gn1;
                 }
             }
         }
@@ -1029,7 +1052,7 @@ __global__ void overflow_rows_zero_kernel(const unsigned *__restrict__ list, con
                                           float *__restrict__ gtri) {
     const unsigned n = counters->overflow_list_len;
     for (unsigned o = blockIdx.x; o < n; o += gridDim.x)
-        for (int i = threadIdx.x; i < kNV; i += blockDim.x) gtri[(size_t)list[o] * kNV + i] = 0.f;
+        for (int i = threadIdx.x; i < kGtriStride; i += blockDim.x) gtri[(size_t)list[o] * kGtriStride + i] = 0.f;
 }
 
 constexpr unsigned kBigPairs = 16;
@@ -1055,7 +1078,7 @@ __global__ void pair_reduce_kernel(const unsigned *__restrict__ pair_off, int nt
 #pragma unroll
             for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
 #pragma unroll
-    for (int q = 0; q < kNV; ++q) gtri[(size_t)i * kNV + q] = acc[q];
+    for (int q = 0; q < kNV; ++q) gtri[(size_t)i * kGtriStride + gtri_slot(q)] = acc[q];
 }
 
 __global__ __launch_bounds__(256) void big_pair_reduce_kernel(const unsigned *__restrict__ pair_off,
@@ -1075,7 +1098,7 @@ __global__ __launch_bounds__(256) void big_pair_reduce_kernel(const unsigned *__
             if (pair_flag[p])
 #pragma unroll
                 for (int q = 0; q < kNV; ++q) acc[q] += pair_sums[(size_t)p * kNV + q];
-        block_sum_store<4>(acc, gtri + (size_t)i * kNV);
+        block_sum_store<4>(acc, gtri + (size_t)i * kGtriStride, [](int q) { return gtri_slot(q); });
         __syncthreads();
     }
 }
@@ -1106,13 +1129,12 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
         float gc[3] = {0, 0, 0};
         for (int c = c0; c < c1; ++c) {
             const int e = vc_list[c];
-            const float *row = gtri + (size_t)(v.setup_off + (e >> 2)) * kNV;
-            const int corner = e & 3;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                gv[k] += row[corner * 3 + k];
-                gc[k] += row[9 + corner * 3 + k];
-            }
+            // the corner's record: world x y z, clip x | clip y w
+            const float *rec = gtri + (size_t)(v.setup_off + (e >> 2)) * kGtriStride + (e & 3) * 8;
+            const float4 a = *(const float4 *)rec;
+            const float2 b = *(const float2 *)(rec + 4);
+            gv[0] += a.x; gv[1] += a.y; gv[2] += a.z;
+            gc[0] += a.w; gc[1] += b.x; gc[2] += b.y;
         }
         if (in) {
             const float4 ga = gclip[v.clip_off + vl];
@@ -1152,8 +1174,8 @@ __global__ void albedo_gather_kernel(const ViewConst *__restrict__ views, int L,
     for (int s = scene_views_off[b]; s < scene_views_off[b + 1]; ++s) {
         const int vi = scene_views[s];
         if (vi < L) continue;
-        const float *row = gtri + (size_t)(views[vi].setup_off + fl) * kNV;
-        for (int c = 0; c < C; ++c) acc[c] += row[18 + c];
+        const float *row = gtri + (size_t)(views[vi].setup_off + fl) * kGtriStride;
+        for (int c = 0; c < C; ++c) acc[c] += row[gtri_slot(18 + c)];
     }
     for (int c = 0; c < C; ++c) galbedo[(size_t)(scene_face_off[b] + fl) * C + c] = acc[c];
 }
