@@ -91,15 +91,16 @@ __device__ __forceinline__ BaryFull bary_full(float4 c0, float4 c1, float4 c2, f
 // gb (d loss / d barycentrics) -> gradient w.r.t. clip (x, y, w) of the 3 corners: out[3*i + {0,1,2}]
 __device__ __forceinline__ void bary_backward(const BaryFull &b, float px, float py, float gb0, float gb1, float gb2,
                                               float out[9]) {
-    const float dotg = (gb0 * b.b0 + gb1 * b.b1) + gb2 * b.b2;
+    // adjoint only: fused multiply-adds
+    const float dotg = fmaf(gb2, b.b2, fmaf(gb1, b.b1, gb0 * b.b0));
     const float rs = grcp(b.s);
     const float gk0 = (gb0 - dotg) * rs, gk1 = (gb1 - dotg) * rs, gk2 = (gb2 - dotg) * rs;
-    const float ga0x = -gk1 * b.a2y + gk2 * b.a1y, ga0y = gk1 * b.a2x - gk2 * b.a1x;
-    const float ga1x = gk0 * b.a2y - gk2 * b.a0y, ga1y = -gk0 * b.a2x + gk2 * b.a0x;
-    const float ga2x = -gk0 * b.a1y + gk1 * b.a0y, ga2y = gk0 * b.a1x - gk1 * b.a0x;
-    out[0] = ga0x; out[1] = ga0y; out[2] = -px * ga0x - py * ga0y;
-    out[3] = ga1x; out[4] = ga1y; out[5] = -px * ga1x - py * ga1y;
-    out[6] = ga2x; out[7] = ga2y; out[8] = -px * ga2x - py * ga2y;
+    const float ga0x = fmaf(gk2, b.a1y, -gk1 * b.a2y), ga0y = fmaf(gk1, b.a2x, -gk2 * b.a1x);
+    const float ga1x = fmaf(gk0, b.a2y, -gk2 * b.a0y), ga1y = fmaf(gk2, b.a0x, -gk0 * b.a2x);
+    const float ga2x = fmaf(gk1, b.a0y, -gk0 * b.a1y), ga2y = fmaf(gk0, b.a1x, -gk1 * b.a0x);
+    out[0] = ga0x; out[1] = ga0y; out[2] = -fmaf(px, ga0x, py * ga0y);
+    out[3] = ga1x; out[4] = ga1y; out[5] = -fmaf(px, ga1x, py * ga1y);
+    out[6] = ga2x; out[7] = ga2y; out[8] = -fmaf(px, ga2x, py * ga2y);
 }
 
 // ----------------------------------------------------------------------------- camera smoothing^T
@@ -595,7 +596,9 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         const float gvis = srho * lam * l.intensity * cone;
         const float glam = srho * vis * l.intensity * cone;
         const float gndo = ndo > 0.f ? glam : 0.f;
-        gn[0] += gndo * ox; gn[1] += gndo * oy; gn[2] += gndo * oz;
+        // from here on only gradient terms are formed: fused multiply-adds
+        // (nothing below feeds a forward value or a decision)
+        gn[0] = fmaf(gndo, ox, gn[0]); gn[1] = fmaf(gndo, oy, gn[1]); gn[2] = fmaf(gndo, oz, gn[2]);
         const float gox = gndo * nx, goy = gndo * ny, goz = gndo * nz;
         // this pixel's gradient w.r.t. the light frame (M, pos, dir), pulled
         // back to the light parameter through the frame's Jacobian at the end
@@ -604,9 +607,9 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         if (l.kind == kDirectional) {
             gdir[0] -= gox; gdir[1] -= goy; gdir[2] -= goz;
         } else {
-            const float od = (ox * gox + oy * goy) + oz * goz;
+            const float od = fmaf(oz, goz, fmaf(oy, goy, ox * gox));
             const float rl = grcp(olen);
-            const float gpx = (gox - ox * od) * rl, gpy = (goy - oy * od) * rl, gpz = (goz - oz * od) * rl;
+            const float gpx = fmaf(-ox, od, gox) * rl, gpy = fmaf(-oy, od, goy) * rl, gpz = fmaf(-oz, od, goz) * rl;
             gpos[0] += gpx; gpos[1] += gpy; gpos[2] += gpz;
             gx[0] -= gpx; gx[1] -= gpy; gx[2] -= gpz;
         }
@@ -628,27 +631,33 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
             }
             const bool clamped = m2 - m1 * m1 < floor_v;
             const float dv_dvar = clamped ? 0.f : dv_dvar_raw;
-            const float gm1 = gvr * (dv_dmu - 2.f * m1 * dv_dvar);
+            const float gm1 = gvr * fmaf(-2.f * m1, dv_dvar, dv_dmu);
             const float gm2 = gvr * dv_dvar;
             // d v / d (receiver depth): through d - mu, through the floor when
             // it binds and follows the warp, and through the warp itself
             float dv_dzw = -dv_dmu;
             if (l.warp_c > 0.f) {
-                if (clamped) dv_dzw += dv_dvar_raw * (2.f * l.min_var * l.warp_c * l.warp_c * zw);
+                if (clamped) dv_dzw = fmaf(dv_dvar_raw, 2.f * l.min_var * l.warp_c * l.warp_c * zw, dv_dzw);
                 dv_dzw *= l.warp_c * zw;
             }
             const float gdepth = gvr * dv_dzw * grcp(l.zfar);
             if (l.kind == kDirectional) {
-                gx[0] += gdepth * l.dir[0]; gx[1] += gdepth * l.dir[1]; gx[2] += gdepth * l.dir[2];
-                gpos[0] -= gdepth * l.dir[0]; gpos[1] -= gdepth * l.dir[1]; gpos[2] -= gdepth * l.dir[2];
-                gdir[0] += gdepth * (x - l.pos[0]); gdir[1] += gdepth * (y - l.pos[1]); gdir[2] += gdepth * (z - l.pos[2]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    gx[k] = fmaf(gdepth, l.dir[k], gx[k]);
+                    gpos[k] = fmaf(-gdepth, l.dir[k], gpos[k]);
+                }
+                gdir[0] = fmaf(gdepth, x - l.pos[0], gdir[0]);
+                gdir[1] = fmaf(gdepth, y - l.pos[1], gdir[1]);
+                gdir[2] = fmaf(gdepth, z - l.pos[2], gdir[2]);
             } else {
                 const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
                 const float dl = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
                 const float rd = grcp(dl);
                 const float ux_ = ddx * rd, uy_ = ddy * rd, uz_ = ddz * rd;
-                gx[0] += gdepth * ux_; gx[1] += gdepth * uy_; gx[2] += gdepth * uz_;
-                gpos[0] -= gdepth * ux_; gpos[1] -= gdepth * uy_; gpos[2] -= gdepth * uz_;
+                gx[0] = fmaf(gdepth, ux_, gx[0]); gx[1] = fmaf(gdepth, uy_, gx[1]); gx[2] = fmaf(gdepth, uz_, gx[2]);
+                gpos[0] = fmaf(-gdepth, ux_, gpos[0]); gpos[1] = fmaf(-gdepth, uy_, gpos[1]);
+                gpos[2] = fmaf(-gdepth, uz_, gpos[2]);
             }
             // bilinear scatter to the moment maps
             if (DIRECT) {
@@ -663,51 +672,61 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                 hits[q] = MapHit{ixs, iys, fx, fy, gm1, gm2};
             }
             // the map position moves with x and with the light camera
-            const float dm1fx = (1.f - fy) * (t01.x - t00.x) + fy * (t11.x - t10.x);
-            const float dm1fy = (1.f - fx) * (t10.x - t00.x) + fx * (t11.x - t01.x);
-            const float dm2fx = (1.f - fy) * (t01.y - t00.y) + fy * (t11.y - t10.y);
-            const float dm2fy = (1.f - fx) * (t10.y - t00.y) + fx * (t11.y - t01.y);
-            const float gsx = gm1 * dm1fx + gm2 * dm2fx;
-            const float gsy = gm1 * dm1fy + gm2 * dm2fy;
+            // d m / d(fx, fy): each a lerp of two texel differences
+            const float a1 = t01.x - t00.x, b1 = t11.x - t10.x, c1 = t10.x - t00.x, d1 = t11.x - t01.x;
+            const float a2 = t01.y - t00.y, b2 = t11.y - t10.y, c2 = t10.y - t00.y, d2 = t11.y - t01.y;
+            const float dm1fx = fmaf(fy, b1 - a1, a1), dm1fy = fmaf(fx, d1 - c1, c1);
+            const float dm2fx = fmaf(fy, b2 - a2, a2), dm2fy = fmaf(fx, d2 - c2, c2);
             const float hs = 0.5f * S;
+            const float gsx = fmaf(gm2, dm2fx, gm1 * dm1fx) * hs;
+            const float gsy = fmaf(gm2, dm2fy, gm1 * dm1fy) * hs;
             const float rw = grcp(cw);
-            gcx = gsx * hs * rw;
-            gcy = -gsy * hs * rw;
-            gcw = (-gsx * hs * cx + gsy * hs * cy) * (rw * rw);
-            for (int k = 0; k < 3; ++k) gx[k] += (M[k] * gcx + M[4 + k] * gcy) + M[12 + k] * gcw;
+            gcx = gsx * rw;
+            gcy = -gsy * rw;
+            gcw = fmaf(-gsx, cx, gsy * cy) * (rw * rw);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gx[k] = fmaf(M[12 + k], gcw, fmaf(M[4 + k], gcy, fmaf(M[k], gcx, gx[k])));
         }
         // dL/dM = (gcx, gcy, 0, gcw) outer [x, 1]; with dL/dpos, dL/ddir through J
         const float *J = jac + (size_t)kJac * render_lights[R.light_begin + q];
         const float xh[4] = {x, y, z, 1.f};
+        // per parameter j: sum over rows r in (x, y, w) of g_r (J_r(j) . [x, 1]),
+        // plus the position and direction terms
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            float a = 0.f;
+            float u[3];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                a += xh[k] * ((gcx * J[3 * k + j] + gcy * J[3 * (4 + k) + j]) + gcw * J[3 * (12 + k) + j]);
+            for (int r = 0; r < 3; ++r) {
+                const int row = r == 0 ? 0 : r == 1 ? 4 : 12;
+                u[r] = fmaf(xh[2], J[3 * (row + 2) + j],
+                            fmaf(xh[1], J[3 * (row + 1) + j], fmaf(xh[0], J[3 * row + j], J[3 * (row + 3) + j])));
+            }
+            float a = fmaf(gcw, u[2], fmaf(gcy, u[1], fmaf(gcx, u[0], accl[q][j])));
 #pragma unroll
-            for (int i = 0; i < 3; ++i) a += gpos[i] * J[3 * (16 + i) + j] + gdir[i] * J[3 * (19 + i) + j];
-            accl[q][j] += a;
+            for (int i = 0; i < 3; ++i) a = fmaf(gdir[i], J[3 * (19 + i) + j], fmaf(gpos[i], J[3 * (16 + i) + j], a));
+            accl[q][j] = a;
         }
     }
     // albedo
     for (int c = 0; c < 3; ++c) vals[18 + c] = c < C ? g[c] * shade : 0.f;
     // normal: n = cr / |cr|, cr = e1 x e2
-    const float ndg = (nx * gn[0] + ny * gn[1]) + nz * gn[2];
+    const float ndg = fmaf(nz, gn[2], fmaf(ny, gn[1], nx * gn[0]));
     const float rn = grcp(nn);
-    const float gcr[3] = {(gn[0] - nx * ndg) * rn, (gn[1] - ny * ndg) * rn, (gn[2] - nz * ndg) * rn};
-    const float ge1[3] = {e2y * gcr[2] - e2z * gcr[1], e2z * gcr[0] - e2x * gcr[2], e2x * gcr[1] - e2y * gcr[0]};
-    const float ge2[3] = {gcr[1] * e1z - gcr[2] * e1y, gcr[2] * e1x - gcr[0] * e1z, gcr[0] * e1y - gcr[1] * e1x};
+    const float gcr[3] = {fmaf(-nx, ndg, gn[0]) * rn, fmaf(-ny, ndg, gn[1]) * rn, fmaf(-nz, ndg, gn[2]) * rn};
+    const float ge1[3] = {fmaf(e2y, gcr[2], -e2z * gcr[1]), fmaf(e2z, gcr[0], -e2x * gcr[2]),
+                          fmaf(e2x, gcr[1], -e2y * gcr[0])};
+    const float ge2[3] = {fmaf(gcr[1], e1z, -gcr[2] * e1y), fmaf(gcr[2], e1x, -gcr[0] * e1z),
+                          fmaf(gcr[0], e1y, -gcr[1] * e1x)};
     // x = sum b_i v_i
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        vals[k] = b.b0 * gx[k] - ge1[k] - ge2[k];
-        vals[3 + k] = b.b1 * gx[k] + ge1[k];
-        vals[6 + k] = b.b2 * gx[k] + ge2[k];
+        vals[k] = fmaf(b.b0, gx[k], -ge1[k]) - ge2[k];
+        vals[3 + k] = fmaf(b.b1, gx[k], ge1[k]);
+        vals[6 + k] = fmaf(b.b2, gx[k], ge2[k]);
     }
-    const float gb0 = (gx[0] * v0[0] + gx[1] * v0[1]) + gx[2] * v0[2];
-    const float gb1 = (gx[0] * v1[0] + gx[1] * v1[1]) + gx[2] * v1[2];
-    const float gb2 = (gx[0] * v2[0] + gx[1] * v2[1]) + gx[2] * v2[2];
+    const float gb0 = fmaf(gx[2], v0[2], fmaf(gx[1], v0[1], gx[0] * v0[0]));
+    const float gb1 = fmaf(gx[2], v1[2], fmaf(gx[1], v1[1], gx[0] * v1[0]));
+    const float gb2 = fmaf(gx[2], v2[2], fmaf(gx[1], v2[1], gx[0] * v2[0]));
     float gc[9];
     bary_backward(b, px, py, gb0, gb1, gb2, gc);
 #pragma unroll
