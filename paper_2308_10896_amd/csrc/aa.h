@@ -129,7 +129,8 @@ __device__ __forceinline__ bool aa_eval(const ViewConst &v, const TriSetup *__re
 // the pairs can be smoothed at all: different triangles and a front
 // triangle with a silhouette edge in this view.  All neighbour keys are
 // loaded together, then all silhouette bytes, so a sample waits for two
-// dependent loads instead of two per neighbour.  The view must have faces.
+// dependent loads instead of two per neighbour (one when no lane of its
+// wave has a differing neighbour).  The view must have faces.
 struct AANeighbours {
     unsigned long long kn[4];
     int q[4];
@@ -148,13 +149,22 @@ __device__ __forceinline__ AANeighbours aa_neighbours(const ViewConst &v, const 
         n.q[d] = inb[d] ? jn * v.W + in_ : j * v.W + i;
         n.kn[d] = kv[n.q[d]];
     }
-    unsigned char sil[4];
+    bool differ[4], any = false;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const bool differ = inb[d] && (unsigned)n.kn[d] != (unsigned)ks;
-        const unsigned front = ks < n.kn[d] ? (unsigned)ks : (unsigned)n.kn[d];
-        sil[d] = silm[v.setup_off + (differ ? front : 0u)];
-        n.cand[d] = differ && sil[d] != 0;
+        differ[d] = inb[d] && (unsigned)n.kn[d] != (unsigned)ks;
+        any = any || differ[d];
+        n.cand[d] = false;
+    }
+    // a wave inside one triangle (most of a ground plane) waits for no
+    // silhouette byte at all
+    if (__ballot(any) != 0ull) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const unsigned front = ks < n.kn[d] ? (unsigned)ks : (unsigned)n.kn[d];
+            const unsigned char sil = differ[d] ? silm[v.setup_off + front] : (unsigned char)0;
+            n.cand[d] = differ[d] && sil != 0;
+        }
     }
     return n;
 }

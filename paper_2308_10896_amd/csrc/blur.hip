@@ -24,9 +24,15 @@
 namespace dsm {
 
 constexpr int kBlurTX = 64;                          // tile width: one column per lane
-constexpr int kBlurTY = 64;                          // tile height
 constexpr int kBlurThreads = 256;
-constexpr int kBlurWaveRows = kBlurTY / (kBlurThreads / kBlurTX);   // output rows per lane
+
+// Tile height for radius R.  The staged tile carries 2R halo rows, so short
+// tiles pay relatively more for wide filters, and tall tiles keep fewer
+// workgroups resident.  Measured on this GPU (stand-alone filter and
+// transpose, 64 x 512^2, 8 x 1024^2 and 3 x 2048^2 maps): 32 rows is
+// fastest for R <= 4 (k <= 9), 64 rows from R = 5 (k >= 11) on; 16 rows is
+// slower everywhere and 128 slower at R = 2.
+__host__ __device__ constexpr int blur_ty(int R) { return R <= 4 ? 32 : 64; }
 
 __device__ __forceinline__ int find_job(const BlurJob *jobs, int njobs, int tile) {
     int lo = 0, hi = njobs - 1;
@@ -45,7 +51,9 @@ struct BlurGeom {
     static constexpr int K = 2 * R + 1;
     static constexpr int H4 = (R + 3) & ~3;
     static constexpr int RWP = kBlurTX + 2 * H4;                    // LDS row stride (floats)
-    static constexpr int RH = kBlurTY + 2 * R;                      // staged rows
+    static constexpr int TY = blur_ty(R);                           // tile height
+    static constexpr int WR = TY / (kBlurThreads / kBlurTX);        // output rows per lane
+    static constexpr int RH = TY + 2 * R;                           // staged rows
     static constexpr int NQ = RH * (kBlurTX / 4);                   // interior quads per channel
     static constexpr int QPT = (2 * NQ + kBlurThreads - 1) / kBlurThreads;
     static constexpr int NH = RH * 2 * R;                           // halo texels per channel
@@ -70,7 +78,7 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
     const int S = J.S;
     const int map = jobs ? 0 : item / per_map;
     const int t = jobs ? item - J.tile_off : item - map * per_map;
-    const int x0 = (t % J.tiles_x) * kBlurTX, y0 = (t / J.tiles_x) * kBlurTY;
+    const int x0 = (t % J.tiles_x) * kBlurTX, y0 = (t / J.tiles_x) * G::TY;
     const int tid = (int)threadIdx.x;
     const size_t plane = (size_t)S * S;
     const long long map_shift = (long long)map * 2 * (long long)plane;
@@ -243,7 +251,7 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
     }
     const int lane = tid & (kBlurTX - 1);
     const int x = x0 + lane;
-    const int lr0 = (tid / kBlurTX) * kBlurWaveRows;          // first output row of this wave (tile-local)
+    const int lr0 = (tid / kBlurTX) * G::WR;                  // first output row of this wave (tile-local)
     // horizontal filter of staged row l at this lane's column
     auto hfilter = [&](int l, float &ha, float &hb) {
         const float *pa = &tile_s[0][l][H4 - R + lane], *pb = &tile_s[1][l][H4 - R + lane];
@@ -276,7 +284,7 @@ __global__ __launch_bounds__(kBlurThreads) void blur_kernel(const BlurJob *__res
         __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int i = 0; i < kBlurWaveRows; ++i) {
+    for (int i = 0; i < G::WR; ++i) {
         hfilter(lr0 + 2 * R + i, ra[2 * R], rb[2 * R]);
         const int yy = y0 + lr0 + i;
         float va = 0.f, vb = 0.f;
@@ -339,8 +347,8 @@ static hipError_t launch_r(int R, dim3 grid, const BlurJob *jobs, int njobs, con
 }
 
 int blur_tiles_x(int S) { return (S + kBlurTX - 1) / kBlurTX; }
-int blur_tiles(int S, int) { return blur_tiles_x(S) * ((S + kBlurTY - 1) / kBlurTY); }
-int blur_tile_height(int) { return kBlurTY; }
+int blur_tiles(int S, int R) { return blur_tiles_x(S) * ((S + blur_ty(R) - 1) / blur_ty(R)); }
+int blur_tile_height(int R) { return blur_ty(R); }
 
 // jobs_dev: njobs jobs of one radius R (job.k == 2R + 1), tile offsets from 0.
 hipError_t launch_blur(const BlurJob *jobs_dev, int njobs, int total_tiles, const float *in, float *out,

@@ -106,7 +106,7 @@ __device__ __forceinline__ void bary_backward(const BaryFull &b, float px, float
 // ----------------------------------------------------------------------------- camera smoothing^T
 
 template <int C>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void aa_camera_backward_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void aa_camera_backward_kernel(
     const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders, const TriSetup *__restrict__ setup,
     const int *__restrict__ faces, const unsigned char *__restrict__ silm, const float *__restrict__ verts,
     const unsigned long long *__restrict__ keys, const float *__restrict__ img0, const float *__restrict__ gimg,
