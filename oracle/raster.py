@@ -21,8 +21,10 @@ project's reading where the paper is silent:
   for the directed edge a -> b (inside positive); a sample on an edge is
   covered only for top edges (dy == 0, dx > 0) and left edges (dy < 0);
 * depth z01_i = 0.5 * ndc.z_i + 0.5, interpolated as
-  (z0 + b1*(z1 - z0)) + b2*(z2 - z0) with b_e = f32(E_e) / f32(A); samples with
-  z01 outside [0, 1] are dropped;
+  (z0 + b1*(z1 - z0)) + b2*(z2 - z0) with b_e = f32(E_e) * rA, where
+  rA = f32(1) / f32(A) is the correctly rounded float32 reciprocal of the
+  doubled area, formed once per triangle; samples with z01 outside [0, 1]
+  are dropped;
 * key = bits(z01) << 32 | triangle index; the smallest key wins (ties in
   depth go to the lower triangle index); background key = 2^64 - 1.
 
@@ -135,9 +137,9 @@ def coverage(st):
             v = edge_value(st, t, e, px, py)
             E.append(v)
             inside &= (v > 0) | ((v == 0) & top_left(st, t, e))
-        A = F(st['A'][t])
-        b1 = E[1].astype(np.float64).astype(F) / A
-        b2 = E[2].astype(np.float64).astype(F) / A
+        rA = F(1) / F(st['A'][t])
+        b1 = E[1].astype(np.float64).astype(F) * rA
+        b2 = E[2].astype(np.float64).astype(F) * rA
         z0, z1, z2 = st['z'][t]
         z = (z0 + b1 * (z1 - z0)) + b2 * (z2 - z0)
         inside &= (z >= F(0)) & (z <= F(1))

@@ -439,7 +439,7 @@ __global__ void overflow_list_kernel(const unsigned *__restrict__ pair_off, int 
 struct RasterTri {
     int X[3], Y[3];
     float z[3];
-    float fA;
+    float rA;           // correctly rounded float32 1 / A
     unsigned short bx0, by0, bx1, by1;
     unsigned tri;
     int pad;
@@ -448,7 +448,7 @@ struct RasterTri {
 __device__ __forceinline__ RasterTri load_raster_tri(const TriSetup &s, unsigned local) {
     RasterTri r;
     for (int k = 0; k < 3; ++k) { r.X[k] = s.X[k]; r.Y[k] = s.Y[k]; r.z[k] = s.z[k]; }
-    r.fA = (float)(double)s.A;
+    r.rA = 1.0f / (float)(double)s.A;
     r.bx0 = s.bx0; r.by0 = s.by0; r.bx1 = s.bx1; r.by1 = s.by1;
     r.tri = local;
     r.pad = 0;
@@ -475,8 +475,9 @@ __device__ __forceinline__ unsigned long long sample_key(const RasterTri &r, int
     const bool in1 = e1 > 0 || (e1 == 0 && top_left(r.X[2], r.Y[2], r.X[0], r.Y[0]));
     const bool in2 = e2 > 0 || (e2 == 0 && top_left(r.X[0], r.Y[0], r.X[1], r.Y[1]));
     if (!(in0 && in1 && in2)) return kBgKey;
-    const float b1 = (float)(double)e1 / r.fA;
-    const float b2 = (float)(double)e2 / r.fA;
+    // b_e = f32(E_e) * (1 / A): one reciprocal per triangle, one product per sample
+    const float b1 = (float)(double)e1 * r.rA;
+    const float b2 = (float)(double)e2 * r.rA;
     const float z = (r.z[0] + b1 * (r.z[1] - r.z[0])) + b2 * (r.z[2] - r.z[0]);
     if (!(z >= 0.0f && z <= 1.0f)) return kBgKey;
     const unsigned bits = __float_as_uint(z) & 0x7FFFFFFFu;
