@@ -29,32 +29,43 @@ sys.path.insert(0, ROOT)
 METRIC = "shadowed fwd+bwd renders/sec at 512² (batched vs plain, 1 MI355X); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic per launch of the targeted kernels on this workload, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this
-# script (profiles/cfg2_hbm_traffic_pmc.md).  Each counter is scaled by what
-# it reads for a plain 128 MiB device-to-device copy in the same runs
-# (FETCH_SIZE reads 65548.0 KiB and WRITE_SIZE 131072 KiB for 131072 KiB
-# moved each way).  A record is only used while the kernel's sources hash to
-# the value they had when the counters were taken.
-PMC_FETCH_SCALE = 131072.0 / 65548.0
-PMC_WRITE_SCALE = 131072.0 / 131072.0
-PMC_TRAFFIC = {
-    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=66045.6, write_kib=131072.0,
-                   sources=('blur.hip', 'dsm_internal.h'), sha1='539cac5eb6138bfe'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65732.1, write_kib=131072.0,
-                       sources=('blur.hip', 'dsm_internal.h'), sha1='539cac5eb6138bfe'),
-    'lookup': dict(kernel='lookup_kernel', fetch_kib=147629.7, write_kib=65536.0,
-                   sources=('shade.hip', 'dsm_internal.h'), sha1='eb1fd9388ed8d3d8'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=117630.8, write_kib=100958.9,
-                       sources=('grad.hip', 'dsm_internal.h'), sha1='dbeeadd925665920'),
+# Counter records per launch of the targeted kernels on this workload, from
+# rocprofv3 --pmc passes of this script, one counter group per run
+# (profiles/cfg2_counters_pmc.md gives the commands and the tables):
+#
+# * fetch_kib / write_kib: FETCH_SIZE and WRITE_SIZE (KiB per dispatch).
+#   Each is scaled by what it reads for a plain 128 MiB device-to-device copy
+#   in the same runs (PMC_COPY): FETCH_SIZE counts a 128-byte read request
+#   as 64 bytes, so the copy reads back half its size;
+# * rd_bytes / wr_bytes: the same traffic from the per-request-size counters
+#   (32 TCC_EA0_RDREQ_32B + 64 TCC_EA0_RDREQ_64B + 128 TCC_EA0_RDREQ_128B;
+#   32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B) + 64 TCC_EA0_WRREQ_64B), exact
+#   for the copy (factor 1.00) and for gathers that mix request sizes;
+# * waves, valu_per_wave (SQ_INSTS_VALU / SQ_WAVES), valu_busy
+#   (4 SQ_ACTIVE_INST_VALU over the 1024 SIMDs' cycles: a wave64 VALU
+#   instruction occupies a 16-lane SIMD for 4 cycles) and occupancy
+#   (waves resident per CU, 4 SQ_WAVE_CYCLES / GRBM_GUI_ACTIVE per XCD).
+#
+# A record is used only while the kernel's sources hash to the value they
+# had when the counters were taken (and at tile side 8, where they were).
+PMC_COPY = dict(fetch_kib=65547.6, write_kib=131072.0, moved_kib=131072.0)
+PMC = {
+    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=65737.1, write_kib=131072.0, rd_bytes=134552486, wr_bytes=134217728, waves=32768, valu_per_wave=716.2, valu_busy=0.616, occupancy=19.2, sources=('blur.hip', 'dsm_internal.h'), sha1='405115fd525bbcd9'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65622.3, write_kib=131072.0, rd_bytes=134310170, wr_bytes=134217728, waves=32768, valu_per_wave=943.1, valu_busy=0.804, occupancy=20.1, sources=('blur.hip', 'dsm_internal.h'), sha1='405115fd525bbcd9'),
+    'lookup': dict(kernel='lookup_kernel<2>', fetch_kib=200700.7, write_kib=65536.0, rd_bytes=410715456, wr_bytes=67108864, waves=131072, valu_per_wave=532.6, valu_busy=1.088, occupancy=26.0, sources=('shade.hip', 'dsm_internal.h'), sha1='3fe02bb4ae91448a'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=117288.4, write_kib=120174.7, rd_bytes=239959936, wr_bytes=123059296, waves=262144, valu_per_wave=898.0, valu_busy=0.801, occupancy=14.8, sources=('grad.hip', 'dsm_internal.h'), sha1='d11eea9c531a87a1'),
 }
 
+# Issue peak of the vector ALUs: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per
+# wave64 instruction.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
-def pmc_traffic(stage, tile):
-    """HBM bytes per launch measured by the counters, or None when no record
-    matches the current kernel sources (and tile side 8 they were taken at)."""
+
+def pmc_record(stage, tile):
+    """The counter record of a stage's kernel, or None when there is none for
+    the current kernel sources (and tile side 8)."""
     import hashlib
-    rec = PMC_TRAFFIC.get(stage)
+    rec = PMC.get(stage)
     if rec is None or tile != 8:
         return None
     m = hashlib.sha1()
@@ -63,7 +74,14 @@ def pmc_traffic(stage, tile):
             m.update(fh.read())
     if m.hexdigest()[:16] != rec['sha1']:
         return None
-    return 1024.0 * (rec['fetch_kib'] * PMC_FETCH_SCALE + rec['write_kib'] * PMC_WRITE_SCALE)
+    return rec
+
+
+def pmc_traffic(rec):
+    """HBM bytes per launch: FETCH_SIZE / WRITE_SIZE scaled by the copy."""
+    fs = PMC_COPY['moved_kib'] / PMC_COPY['fetch_kib']
+    ws = PMC_COPY['moved_kib'] / PMC_COPY['write_kib']
+    return 1024.0 * (rec['fetch_kib'] * fs + rec['write_kib'] * ws)
 
 
 def parse():
@@ -293,7 +311,9 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
     tile = int(plan.info.tile_size)
     for name, b in algo.items():
         us = 1000.0 * stages[name]
-        tr = pmc_traffic(name, tile)
+        rec = pmc_record(name, tile)
+        tr = None if rec is None else pmc_traffic(rec)
+        tx = None if rec is None else rec['rd_bytes'] + rec['wr_bytes']
         kernels[name] = dict(us=round(us, 2), bytes=b, gbs=round(b / (us * 1e-6) / 1e9, 1),
                              frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
         if stages_cold is not None:
@@ -301,7 +321,18 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
             kernels[name].update(us_cold=round(us_cold, 2), gbs_cold=round(b / (us_cold * 1e-6) / 1e9, 1),
                                  frac_cold=round(b / (us_cold * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
         kernels[name].update(traffic=None if tr is None else round(tr),
-                             traffic_gbs=None if tr is None else round(tr / (us * 1e-6) / 1e9, 1))
+                             traffic_gbs=None if tr is None else round(tr / (us * 1e-6) / 1e9, 1),
+                             traffic_by_request_size=None if tx is None else round(tx),
+                             gbs_counter_bytes=None if tx is None else round(tx / (us * 1e-6) / 1e9, 1))
+        if rec is not None:
+            # counter-measured vector-ALU issue: instructions per launch at
+            # the issue peak, against this launch's time
+            insts = rec['valu_per_wave'] * rec['waves']
+            kernels[name]['valu'] = {
+                'insts_per_wave': rec['valu_per_wave'], 'waves': rec['waves'],
+                'issue_bound_us': round(insts / VALU_ISSUE_PEAK * 1e6, 1),
+                'issue_frac': round(insts / VALU_ISSUE_PEAK / (us * 1e-6), 3),
+                'busy': rec['valu_busy'], 'waves_per_cu': rec['occupancy']}
     reps = 20
     with torch.cuda.stream(stream):
         maps = torch.stack([plan.light_maps(saved, scratch, l, 1) for l in range(n)]).contiguous()
@@ -319,8 +350,12 @@ def kernel_timings(plan, batch, stream, verts, lp, alb, saved, scratch, images, 
         copy_gbs = 2.0 * maps.numel() * 4 / (t / reps) / 1e9
     dom = max(kernels, key=lambda k: kernels[k]['us'])
     d = kernels[dom]
+    # achieved / frac: algorithmic bytes per launch over the launch time;
+    # achieved_counter_bytes: the bytes the counters saw over the same time
     roof = {'kernel': dom, 'bound': 'hbm', 'achieved': d['gbs'], 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
             'frac': d['frac'], 'traffic': d['traffic'],
+            'traffic_by_request_size': d['traffic_by_request_size'],
+            'achieved_counter_bytes': d['gbs_counter_bytes'], 'valu': d.get('valu'),
             'kernels': kernels,
             'copy_gbs': round(copy_gbs, 1)}
     return {'stages_us': {k: round(1000.0 * v, 2) for k, v in stages.items()},
