@@ -436,49 +436,65 @@ __global__ void overflow_list_kernel(const unsigned *__restrict__ pair_off, int 
 
 // ----------------------------------------------------------------------------- raster
 
+// A triangle as the tile raster tests it: each edge function in plane form,
+// E_e(px, py) = a px + b py + c with a = -dy, b = dx, c = dy xa - dx ya for
+// the directed edge a -> b opposite vertex e.  With fixed-point coordinates
+// below 2^23 and differences below 2^24 every term and every partial sum is
+// an integer below 2^49, so float64 holds the coefficients and evaluates
+// E_e exactly with two fused multiply-adds: the same value, and the same
+// inside / top-left / depth results, as the 64-bit integer form.  a and b
+// (below 2^24) are kept as int32 to keep the LDS record small.
 struct RasterTri {
-    int X[3], Y[3];
-    float z[3];
+    double c[3];
+    int a[3], b[3];
+    float z0, dz1, dz2;     // z0, z1 - z0, z2 - z0
     float rA;           // correctly rounded float32 1 / A
     unsigned short bx0, by0, bx1, by1;
     unsigned tri;
-    int pad;
+    int top_left;       // bit e: edge e is a top or left edge
 };
-
-__device__ __forceinline__ RasterTri load_raster_tri(const TriSetup &s, unsigned local) {
-    RasterTri r;
-    for (int k = 0; k < 3; ++k) { r.X[k] = s.X[k]; r.Y[k] = s.Y[k]; r.z[k] = s.z[k]; }
-    r.rA = 1.0f / (float)(double)s.A;
-    r.bx0 = s.bx0; r.by0 = s.by0; r.bx1 = s.bx1; r.by1 = s.by1;
-    r.tri = local;
-    r.pad = 0;
-    return r;
-}
-
-__device__ __forceinline__ long long edge_fn(int xa, int ya, int xb, int yb, int px, int py) {
-    return (long long)(xb - xa) * (py - ya) - (long long)(yb - ya) * (px - xa);
-}
 
 __device__ __forceinline__ bool top_left(int xa, int ya, int xb, int yb) {
     const int dx = xb - xa, dy = yb - ya;
     return dy < 0 || (dy == 0 && dx > 0);
 }
 
+__device__ __forceinline__ RasterTri load_raster_tri(const TriSetup &s, unsigned local) {
+    RasterTri r;
+    r.top_left = 0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int ia = (e + 1) % 3, ib = (e + 2) % 3;
+        const int xa = s.X[ia], ya = s.Y[ia], dx = s.X[ib] - xa, dy = s.Y[ib] - ya;
+        r.a[e] = -dy;
+        r.b[e] = dx;
+        r.c[e] = (double)((long long)dy * xa - (long long)dx * ya);
+        r.top_left |= top_left(xa, ya, s.X[ib], s.Y[ib]) ? 1 << e : 0;
+    }
+    r.z0 = s.z[0];
+    r.dz1 = s.z[1] - s.z[0];
+    r.dz2 = s.z[2] - s.z[0];
+    r.rA = 1.0f / (float)(double)s.A;
+    r.bx0 = s.bx0; r.by0 = s.by0; r.bx1 = s.bx1; r.by1 = s.by1;
+    r.tri = local;
+    return r;
+}
+
 // Key of triangle r at pixel (i, j), or kBgKey when not covered.
 __device__ __forceinline__ unsigned long long sample_key(const RasterTri &r, int i, int j) {
     if (i < r.bx0 || i > r.bx1 || j < r.by0 || j > r.by1) return kBgKey;
-    const int px = i * kSub + kSub / 2, py = j * kSub + kSub / 2;
-    const long long e0 = edge_fn(r.X[1], r.Y[1], r.X[2], r.Y[2], px, py);
-    const long long e1 = edge_fn(r.X[2], r.Y[2], r.X[0], r.Y[0], px, py);
-    const long long e2 = edge_fn(r.X[0], r.Y[0], r.X[1], r.Y[1], px, py);
-    const bool in0 = e0 > 0 || (e0 == 0 && top_left(r.X[1], r.Y[1], r.X[2], r.Y[2]));
-    const bool in1 = e1 > 0 || (e1 == 0 && top_left(r.X[2], r.Y[2], r.X[0], r.Y[0]));
-    const bool in2 = e2 > 0 || (e2 == 0 && top_left(r.X[0], r.Y[0], r.X[1], r.Y[1]));
+    const double px = (double)(i * kSub + kSub / 2), py = (double)(j * kSub + kSub / 2);
+    const double e0 = fma((double)r.a[0], px, fma((double)r.b[0], py, r.c[0]));
+    const double e1 = fma((double)r.a[1], px, fma((double)r.b[1], py, r.c[1]));
+    const double e2 = fma((double)r.a[2], px, fma((double)r.b[2], py, r.c[2]));
+    const bool in0 = e0 > 0.0 || (e0 == 0.0 && (r.top_left & 1));
+    const bool in1 = e1 > 0.0 || (e1 == 0.0 && (r.top_left & 2));
+    const bool in2 = e2 > 0.0 || (e2 == 0.0 && (r.top_left & 4));
     if (!(in0 && in1 && in2)) return kBgKey;
     // b_e = f32(E_e) * (1 / A): one reciprocal per triangle, one product per sample
-    const float b1 = (float)(double)e1 * r.rA;
-    const float b2 = (float)(double)e2 * r.rA;
-    const float z = (r.z[0] + b1 * (r.z[1] - r.z[0])) + b2 * (r.z[2] - r.z[0]);
+    const float b1 = (float)e1 * r.rA;
+    const float b2 = (float)e2 * r.rA;
+    const float z = (r.z0 + b1 * r.dz1) + b2 * r.dz2;
     if (!(z >= 0.0f && z <= 1.0f)) return kBgKey;
     const unsigned bits = __float_as_uint(z) & 0x7FFFFFFFu;
     return ((unsigned long long)bits << 32) | r.tri;
