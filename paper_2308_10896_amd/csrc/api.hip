@@ -758,7 +758,7 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
 
     DSM_MARK(DSM_STAGE_BWD_SETUP);
     DSM_TRY(zero_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, s));   // big count, gM, silhouette gclip
-    // pair flags: the camera tile walks set only the flags of pairs that got a sum
+    // pair flags: the 8x8 tile walks set only the flags of pairs that got a sum
     DSM_TRY(zero_async(pair_flag, ((size_t)p->capacity + 3) & ~(size_t)3, s));
     DSM_TRY(launch_overflow_rows_zero(overflow, cnt, gtri, s));
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, jac, nullptr, s));
@@ -780,7 +780,7 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_MARK(DSM_STAGE_LIGHT_ADJ);
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
                                   tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,
-                                  part_light, jac, s));
+                                  part_light, jac, pair_off, p->capacity, s));
     DSM_MARK(DSM_STAGE_VERTEX_GRAD);
     DSM_TRY(launch_vertex_gradients(p->views_d, p->L, p->B, p->max_scene_verts, p->max_scene_faces, p->ntri,
                                     p->capacity, p->scene_vert_off_d, p->scene_face_off_d, p->scene_views_off_d,

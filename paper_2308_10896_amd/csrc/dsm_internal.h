@@ -334,7 +334,7 @@ hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int ma
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
-                                 const float *jac, hipStream_t s);
+                                 const float *jac, const unsigned *pair_off, unsigned capacity, hipStream_t s);
 hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max_verts, int max_faces, int ntri,
                                    unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
                                    const int *scene_views_off, const int *scene_views, const int *vc_off,

@@ -936,8 +936,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
     const unsigned long long *__restrict__ keys, const float *__restrict__ F0, const float *__restrict__ gF1,
     float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
-    float *__restrict__ gtri, float *__restrict__ part_light, const float *__restrict__ jac) {
+    float *__restrict__ gtri, float *__restrict__ part_light, const float *__restrict__ jac,
+    const unsigned *__restrict__ pair_off, unsigned capacity) {
     using TS = TileShape<T>;
+    // one wave per 8x8 tile: pair rows found from the setup records (wave_pair_sums)
+    constexpr bool kWavePairs = T == 8;
     const Blk blk = xcd_block2();
     const int lidx = blk.y;
     const ViewConst &l = views[lidx];
@@ -946,7 +949,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
     const int lt = blk.x;
     if (lt >= l.tiles_x * l.tiles_y) return;     // whole workgroup
     const int gt = l.tile_off + lt;
-    const BinHead head = bin_head(gt, (int)threadIdx.x, tile_start, bins, bin_pair);
+    BinHead head{};
+    if (!kWavePairs) head = bin_head(gt, (int)threadIdx.x, tile_start, bins, bin_pair);
     const int tx = lt % l.tiles_x, ty = lt / l.tiles_x;
     const unsigned long long *kv = keys + l.pix_off;
     const float *f0a = F0 + l.map_off, *f0b = F0 + l.map_off + plane;
@@ -1059,7 +1063,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
         gpar[j] = a;
     }
     block_sum_store<TS::NW>(gpar, part_light + ((long long)l.part_off + lt) * 3);
-    tile_pair_sums<T, 18>(l, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
+    if constexpr (kWavePairs)
+        wave_pair_sums<T, 18>(l, tx, ty, key[0], val[0], act[0], matched[0], setup, pair_off, capacity, pair_flag,
+                              pair_sums);
+    else
+        tile_pair_sums<T, 18>(l, head, bins, bin_pair, key, val, act, matched, pair_flag, pair_sums);
     overflow_rows(l, key, val, act, matched, gtri);
 }
 
@@ -1407,13 +1415,13 @@ hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int ma
                                  const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
-                                 const float *jac, hipStream_t s) {
+                                 const float *jac, const unsigned *pair_off, unsigned capacity, hipStream_t s) {
     if (L == 0 || max_tiles == 0) return hipSuccess;
     const dim3 grid(max_tiles, L);
 #define DSM_LIB(TT)                                                                                                  \
     hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, silm,  \
                        verts, tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,     \
-                       part_light, jac)
+                       part_light, jac, pair_off, capacity)
     if (tile == 8) DSM_LIB(8);
     else if (tile == 16) DSM_LIB(16);
     else DSM_LIB(32);
