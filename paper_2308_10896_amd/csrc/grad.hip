@@ -1154,14 +1154,25 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
         const int vi = scene_views[s];
         const ViewConst &v = views[vi];
         float gc[3] = {0, 0, 0};
-        for (int c = c0; c < c1; ++c) {
-            const int e = vc_list[c];
-            // the corner's record: world x y z, clip x | clip y w
-            const float *rec = gtri + (size_t)(v.setup_off + (e >> 2)) * kGtriStride + (e & 3) * 8;
-            const float4 a = *(const float4 *)rec;
-            const float2 b = *(const float2 *)(rec + 4);
-            gv[0] += a.x; gv[1] += a.y; gv[2] += a.z;
-            gc[0] += a.w; gc[1] += b.x; gc[2] += b.y;
+        // corners four at a time, so that four record loads are in flight
+        for (int c = c0; c < c1; c += 4) {
+            int e[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e[k] = c + k < c1 ? vc_list[c + k] : -1;
+            float4 a[4];
+            float2 b[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                // the corner's record: world x y z, clip x | clip y w
+                const float *rec = gtri + (size_t)(v.setup_off + (max(e[k], 0) >> 2)) * kGtriStride + (e[k] & 3) * 8;
+                a[k] = e[k] >= 0 ? *(const float4 *)rec : make_float4(0.f, 0.f, 0.f, 0.f);
+                b[k] = e[k] >= 0 ? *(const float2 *)(rec + 4) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                gv[0] += a[k].x; gv[1] += a[k].y; gv[2] += a[k].z;
+                gc[0] += a[k].w; gc[1] += b[k].x; gc[2] += b[k].y;
+            }
         }
         if (in) {
             const float4 ga = gclip[v.clip_off + vl];
