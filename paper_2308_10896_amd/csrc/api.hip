@@ -506,11 +506,11 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     // scratch layout
     o = 0;
     p->sc_tile_cnt = o; o = align_up(o + 4 * ((size_t)tiles + 1));
-    p->sc_tile_cursor = o; o = align_up(o + 4 * ((size_t)tiles + 1));
     p->sc_zero_fwd_end = o;
     p->sc_pair_cnt = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
     p->sc_facing = o; o = align_up(o + (size_t)tri + 1);
+    p->sc_pair_slot = o; o = align_up(o + 4 * (size_t)p->capacity);    // each pair's slot in its tile's bin
     p->sc_F1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
     p->sc_fwd_end = o;                 // the forward touches nothing past this
     p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
@@ -671,7 +671,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
                            void *scratch, float *images, hipStream_t s, const StageMarks *marks = nullptr) {
     DevCounters *cnt = at<DevCounters>(saved, p->sv_counters);
     unsigned *tile_cnt = at<unsigned>(scratch, p->sc_tile_cnt);
-    unsigned *tile_cursor = at<unsigned>(scratch, p->sc_tile_cursor);
+    unsigned *pair_slot = at<unsigned>(scratch, p->sc_pair_slot);
     unsigned *pair_cnt = at<unsigned>(scratch, p->sc_pair_cnt);
     unsigned *pair_off = at<unsigned>(saved, p->sv_pair_off);
     unsigned *scan = at<unsigned>(scratch, p->sc_scan);
@@ -691,7 +691,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
 
     DSM_MARK(DSM_STAGE_SETUP);
     DSM_TRY(zero_async(saved, p->sv_zero_end, s));                 // counters
-    DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));           // tile counts and cursors
+    DSM_TRY(zero_async(scratch, p->sc_zero_fwd_end, s));           // tile counts
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, at<float>(saved, p->sv_zc), s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts,
@@ -703,7 +703,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_MARK(DSM_STAGE_BIN);
     DSM_TRY(launch_scan(pair_cnt, pair_off, scan, p->ntri, s));
     DSM_TRY(launch_binning(p->views_d, setup, pair_off, p->ntri, p->capacity, p->tile, tile_cnt, tile_start,
-                           tile_cursor, scan, p->ntiles, bins, bin_pair, overflow, cnt, s));
+                           pair_slot, scan, p->ntiles, bins, bin_pair, overflow, cnt, s));
     DSM_MARK(DSM_STAGE_RASTER);
     DSM_TRY(launch_raster(p->views_d, p->tile_view_d, p->ntiles, p->tile, setup, tile_start, bins, overflow, cnt, cnt,
                           keys, s));

@@ -303,13 +303,16 @@ hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int
 
 // Pairs of triangle i are the tiles of its bounding box in row-major order,
 // numbered pair_off[i] .. pair_off[i+1]-1.  FILL = false counts pairs per
-// tile; FILL = true scatters (triangle, pair) into the tile's bin.  Pairs
-// q0, q0 + step, ... of the triangle are handled by the calling thread.
+// tile and records each pair's slot in its tile (pair_slot, indexed by
+// pair); FILL = true scatters (triangle, pair) to tile_start[tile] + slot,
+// with no atomics.  Pairs q0, q0 + step, ... of the triangle are handled by
+// the calling thread.
 template <bool FILL>
 __device__ __forceinline__ void bin_pairs(const ViewConst *__restrict__ views, const TriSetup &s, int i, unsigned a,
                                           unsigned b, int tile, unsigned q0, unsigned step,
-                                          unsigned *__restrict__ tile_count, const unsigned *__restrict__ tile_start,
-                                          unsigned *__restrict__ bins, unsigned *__restrict__ bin_pair) {
+                                          unsigned *__restrict__ tile_count, unsigned *__restrict__ pair_slot,
+                                          const unsigned *__restrict__ tile_start, unsigned *__restrict__ bins,
+                                          unsigned *__restrict__ bin_pair) {
     const ViewConst &v = views[s.pad2[0]];
     const int tx0 = s.bx0 / tile, tx1 = s.bx1 / tile, ty0 = s.by0 / tile;
     const int ntx = tx1 - tx0 + 1;
@@ -317,11 +320,11 @@ __device__ __forceinline__ void bin_pairs(const ViewConst *__restrict__ views, c
         const int tx = tx0 + (int)(q % ntx), ty = ty0 + (int)(q / ntx);
         const int gt = v.tile_off + ty * v.tiles_x + tx;
         if (!FILL) {
-            atomicAdd(&tile_count[gt], 1u);
+            pair_slot[a + q] = atomicAdd(&tile_count[gt], 1u);
         } else {
-            const unsigned slot = atomicAdd(&tile_count[gt], 1u);
-            bins[tile_start[gt] + slot] = (unsigned)i;
-            bin_pair[tile_start[gt] + slot] = a + q;
+            const unsigned pos = tile_start[gt] + pair_slot[a + q];
+            bins[pos] = (unsigned)i;
+            bin_pair[pos] = a + q;
         }
     }
 }
@@ -363,9 +366,10 @@ constexpr unsigned kBigBin = 32;
 template <bool FILL>
 __global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
                                  const unsigned *__restrict__ pair_off, int ntri, unsigned capacity, int tile,
-                                 unsigned *__restrict__ tile_count, const unsigned *__restrict__ tile_start,
-                                 unsigned *__restrict__ bins, unsigned *__restrict__ bin_pair,
-                                 unsigned *__restrict__ big_list, DevCounters *counters) {
+                                 unsigned *__restrict__ tile_count, unsigned *__restrict__ pair_slot,
+                                 const unsigned *__restrict__ tile_start, unsigned *__restrict__ bins,
+                                 unsigned *__restrict__ bin_pair, unsigned *__restrict__ big_list,
+                                 DevCounters *counters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned a = 0, b = 0;
     if (i < ntri) {
@@ -390,17 +394,19 @@ __global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriS
         toff = v.tile_off;
         tiles_x = v.tiles_x;
     }
-    for (unsigned q = 0; __ballot(q < cnt) != 0; ++q) {   // uniform loop: the wave's largest count
-        const bool has = q < cnt;
-        const int gt = has ? toff + (ty0 + (int)(q / ntx)) * tiles_x + tx0 + (int)(q % ntx) : 0;
-        if (!FILL) {
-            (void)wave_aggregated_slot(has, gt, tile_count);
-        } else {
+    if (!FILL) {
+        for (unsigned q = 0; __ballot(q < cnt) != 0; ++q) {   // uniform loop: the wave's largest count
+            const bool has = q < cnt;
+            const int gt = has ? toff + (ty0 + (int)(q / ntx)) * tiles_x + tx0 + (int)(q % ntx) : 0;
             const unsigned slot = wave_aggregated_slot(has, gt, tile_count);
-            if (has) {
-                bins[tile_start[gt] + slot] = (unsigned)i;
-                bin_pair[tile_start[gt] + slot] = a + q;
-            }
+            if (has) pair_slot[a + q] = slot;
+        }
+    } else {
+        for (unsigned q = 0; q < cnt; ++q) {
+            const int gt = toff + (ty0 + (int)(q / ntx)) * tiles_x + tx0 + (int)(q % ntx);
+            const unsigned pos = tile_start[gt] + pair_slot[a + q];
+            bins[pos] = (unsigned)i;
+            bin_pair[pos] = a + q;
         }
     }
 }
@@ -408,14 +414,14 @@ __global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriS
 template <bool FILL>
 __global__ void bin_big_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
                                const unsigned *__restrict__ pair_off, int tile, unsigned *__restrict__ tile_count,
-                               const unsigned *__restrict__ tile_start, unsigned *__restrict__ bins,
-                               unsigned *__restrict__ bin_pair, const unsigned *__restrict__ big_list,
-                               const DevCounters *counters) {
+                               unsigned *__restrict__ pair_slot, const unsigned *__restrict__ tile_start,
+                               unsigned *__restrict__ bins, unsigned *__restrict__ bin_pair,
+                               const unsigned *__restrict__ big_list, const DevCounters *counters) {
     const unsigned n = counters->big_bin_len;
     for (unsigned o = blockIdx.x; o < n; o += gridDim.x) {
         const int i = (int)big_list[o];
         bin_pairs<FILL>(views, setup[i], i, pair_off[i], pair_off[i + 1], tile, threadIdx.x, blockDim.x, tile_count,
-                        tile_start, bins, bin_pair);
+                        pair_slot, tile_start, bins, bin_pair);
     }
 }
 
@@ -629,7 +635,7 @@ hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const
 
 hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,
                           unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
-                          unsigned *tile_cursor, unsigned *scan_scratch, int ntiles, unsigned *bins,
+                          unsigned *pair_slot, unsigned *scan_scratch, int ntiles, unsigned *bins,
                           unsigned *bin_pair, unsigned *overflow_list, DevCounters *counters, hipStream_t s) {
     hipLaunchKernelGGL(pairs_total_kernel, dim3(1), dim3(1), 0, s, pair_off, ntri, counters);
     // the list of large triangles lives in overflow_list until the overflow list is built below
@@ -637,20 +643,21 @@ hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const u
     const dim3 bgrid(1024);
     if (ntri > 0) {
         hipLaunchKernelGGL(bin_small_kernel<false>, tgrid, dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
-                           tile_count, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
+                           tile_count, pair_slot, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
                            overflow_list, counters);
         hipLaunchKernelGGL(bin_big_kernel<false>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile, tile_count,
-                           (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
+                           pair_slot, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
                            (const unsigned *)overflow_list, (const DevCounters *)counters);
     }
     hipError_t e = launch_scan(tile_count, tile_start, scan_scratch, ntiles, s);
     if (e != hipSuccess) return e;
     if (ntri > 0) {
         hipLaunchKernelGGL(bin_small_kernel<true>, tgrid, dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
-                           tile_cursor, (const unsigned *)tile_start, bins, bin_pair, overflow_list, counters);
-        hipLaunchKernelGGL(bin_big_kernel<true>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile, tile_cursor,
-                           (const unsigned *)tile_start, bins, bin_pair, (const unsigned *)overflow_list,
-                           (const DevCounters *)counters);
+                           (unsigned *)nullptr, pair_slot, (const unsigned *)tile_start, bins, bin_pair, overflow_list,
+                           counters);
+        hipLaunchKernelGGL(bin_big_kernel<true>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile,
+                           (unsigned *)nullptr, pair_slot, (const unsigned *)tile_start, bins, bin_pair,
+                           (const unsigned *)overflow_list, (const DevCounters *)counters);
     }
     if (ntri > 0)
         hipLaunchKernelGGL(overflow_list_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
