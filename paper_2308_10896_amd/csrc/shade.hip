@@ -29,20 +29,9 @@ struct Bary {
 };
 
 // Barycentrics of the point of triangle (c0, c1, c2) that projects to NDC
-// (px, py): sum b_i (x_i - px w_i) = 0, sum b_i (y_i - py w_i) = 0, sum b_i = 1.
-__device__ __forceinline__ Bary persp_bary(float4 c0, float4 c1, float4 c2, float px, float py) {
-    const float a0x = c0.x - px * c0.w, a0y = c0.y - py * c0.w;
-    const float a1x = c1.x - px * c1.w, a1y = c1.y - py * c1.w;
-    const float a2x = c2.x - px * c2.w, a2y = c2.y - py * c2.w;
-    const float k0 = a1x * a2y - a1y * a2x;
-    const float k1 = a2x * a0y - a2y * a0x;
-    const float k2 = a0x * a1y - a0y * a1x;
-    const float s = k0 + k1 + k2;
-    return Bary{k0 / s, k1 / s, k2 / s};
-}
-
-// persp_bary with the hardware reciprocal of the sum (the lookup's form; its
-// adjoint recomputes the same values).
+// (px, py): sum b_i (x_i - px w_i) = 0, sum b_i (y_i - py w_i) = 0, sum b_i = 1,
+// through the hardware reciprocal of the sum (about one ulp; the resolve, the
+// lookup and their adjoints all form them this way).
 __device__ __forceinline__ Bary persp_bary_rcp(float4 c0, float4 c1, float4 c2, float px, float py) {
     const float a0x = c0.x - px * c0.w, a0y = c0.y - py * c0.w;
     const float a1x = c1.x - px * c1.w, a1y = c1.y - py * c1.w;
@@ -85,7 +74,7 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVer
         const float px = ndc_centre(i, S), py = -ndc_centre(j, S);
         const float4 c0 = clip_of(l.M, v0[0], v0[1], v0[2]), c1 = clip_of(l.M, v1[0], v1[1], v1[2]),
                      c2 = clip_of(l.M, v2[0], v2[1], v2[2]);
-        const Bary b = persp_bary(c0, c1, c2, px, py);
+        const Bary b = persp_bary_rcp(c0, c1, c2, px, py);
         const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
         const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
         const float zz = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
