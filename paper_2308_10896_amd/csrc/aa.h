@@ -169,4 +169,41 @@ __device__ __forceinline__ AANeighbours aa_neighbours(const ViewConst &v, const 
     return n;
 }
 
+// Samples listed for the second pass of the smoothing kernels.  The list is
+// cut into segments, each with its own counter, so that the appends of
+// different workgroups do not contend for one address: workgroup b of the
+// first pass (b counted over the whole grid) appends to segment
+// b % kAaSegments, which holds every sample of the workgroups that map to
+// it and so cannot overflow.  The second pass runs one workgroup per
+// segment.
+constexpr int kAaSegments = 4096;
+
+struct AaList {
+    uint2 *items;
+    unsigned *counts;        // kAaSegments counters, zero before the first pass
+    unsigned nseg, segcap;   // segments in use, items per segment
+};
+
+__host__ __device__ inline AaList aa_list_for(uint2 *items, unsigned *counts, long long blocks) {
+    AaList l;
+    l.items = items;
+    l.counts = counts;
+    l.nseg = (unsigned)(blocks < kAaSegments ? blocks : kAaSegments);
+    l.segcap = l.nseg ? (unsigned)(((blocks + l.nseg - 1) / l.nseg) * 256) : 0u;
+    return l;
+}
+
+// Append the active lanes' items to the segment of this workgroup (one
+// atomic per wave).  lin: the workgroup's index over the whole grid.
+__device__ __forceinline__ void wave_append(bool mine, uint2 item, const AaList &l, long long lin) {
+    const unsigned long long m = __ballot(mine);
+    if (m == 0ull) return;
+    const unsigned seg = (unsigned)(lin % l.nseg);
+    const int lane = (int)(threadIdx.x & 63), leader = __ffsll(m) - 1;
+    unsigned first = 0;
+    if (lane == leader) first = atomicAdd(l.counts + seg, (unsigned)__popcll(m));
+    first = (unsigned)__shfl((int)first, leader, 64);
+    if (mine) l.items[(size_t)seg * l.segcap + first + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = item;
+}
+
 }  // namespace dsm

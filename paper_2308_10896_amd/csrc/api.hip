@@ -6,6 +6,7 @@
 #include <new>
 #include <vector>
 
+#include "aa.h"
 #include "dsm_internal.h"
 #include "frames.h"
 #include "plan.h"
@@ -506,11 +507,18 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     // scratch layout
     o = 0;
     p->sc_tile_cnt = o; o = align_up(o + 4 * ((size_t)tiles + 1));
+    p->sc_aa_count = o; o = align_up(o + 4 * (size_t)kAaSegments);      // light smoothing list counters
     p->sc_zero_fwd_end = o;
     p->sc_pair_cnt = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
     p->sc_facing = o; o = align_up(o + (size_t)tri + 1);
     p->sc_pair_slot = o; o = align_up(o + 4 * (size_t)p->capacity);    // each pair's slot in its tile's bin
+    // light-map samples whose smoothing has candidate pairs: the segmented list of the light smoothing
+    // grid (launch_aa_forward cuts it the same way)
+    {
+        const AaList ll = aa_list_for(nullptr, nullptr, (long long)((p->max_light_texels + 255) / 256) * L);
+        p->sc_aa_list = o; o = align_up(o + 8 * (size_t)ll.nseg * ll.segcap + 8);
+    }
     p->sc_F1 = o; o = align_up(o + 4 * (size_t)(maps + padmaps));
     p->sc_fwd_end = o;                 // the forward touches nothing past this
     p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
@@ -672,6 +680,8 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DevCounters *cnt = at<DevCounters>(saved, p->sv_counters);
     unsigned *tile_cnt = at<unsigned>(scratch, p->sc_tile_cnt);
     unsigned *pair_slot = at<unsigned>(scratch, p->sc_pair_slot);
+    uint2 *aa_list = at<uint2>(scratch, p->sc_aa_list);
+    unsigned *aa_count = at<unsigned>(scratch, p->sc_aa_count);
     unsigned *pair_cnt = at<unsigned>(scratch, p->sc_pair_cnt);
     unsigned *pair_off = at<unsigned>(saved, p->sv_pair_off);
     unsigned *scan = at<unsigned>(scratch, p->sc_scan);
@@ -711,7 +721,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_resolve(p->views_d, p->L, p->max_light_texels, tv, keys, F0, s));
     DSM_MARK(DSM_STAGE_LIGHT_AA);
     DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, silm,
-                              verts, keys, F0, F1, 2, s));
+                              verts, keys, F0, F1, 2, aa_list, aa_count, s));
     DSM_MARK(DSM_STAGE_FILTER);
     if (p->has_cube) DSM_TRY(launch_cube_pad(p->views_d, p->L, p->max_cube_padded, p->cube_taps_d, F1, s));
     for (const auto &g : p->blur_groups)
@@ -721,7 +731,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
                           img0, p->C, s));
     DSM_MARK(DSM_STAGE_CAMERA_AA);
     DSM_TRY(launch_aa_forward(false, p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
-                              verts, keys, img0, images, p->C, s));
+                              verts, keys, img0, images, p->C, nullptr, nullptr, s));
     return DSM_OK;
 }
 
@@ -757,7 +767,8 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     float *jac = at<float>(scratch, p->sc_jac);
 
     DSM_MARK(DSM_STAGE_BWD_SETUP);
-    DSM_TRY(zero_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, s));   // big count, gM, silhouette gclip
+    // big count, gM, silhouette gclip
+    DSM_TRY(zero_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, s));
     // pair flags: the 8x8 tile walks set only the flags of pairs that got a sum
     DSM_TRY(zero_async(pair_flag, ((size_t)p->capacity + 3) & ~(size_t)3, s));
     DSM_TRY(launch_overflow_rows_zero(overflow, cnt, gtri, s));

@@ -309,7 +309,8 @@ hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const T
                           const unsigned long long *keys, float *F0, hipStream_t s);
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
                              const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
-                             const unsigned long long *keys, const float *src, float *dst, int C, hipStream_t s);
+                             const unsigned long long *keys, const float *src, float *dst, int C, uint2 *list,
+                             unsigned *count, hipStream_t s);
 hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
                          const int *render_lights, const TriVerts *tv, const float *albedo,
                          const unsigned long long *keys, const float *maps, float *img0, int C, hipStream_t s);

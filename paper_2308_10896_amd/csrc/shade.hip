@@ -91,8 +91,98 @@ __global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVer
 // Light maps: planar 2-channel; grid.y = light view.  Camera images:
 // interleaved C channels; grid.y = render (view = that render's camera).
 // C is a template parameter so that the per-channel values stay in registers.
+//
+// Light maps: two passes.  A sample changes only through a pair whose front
+// triangle has a silhouette edge (a candidate, AANeighbours), which is rare
+// in a shadow map, while testing a candidate waits for three more dependent
+// loads (the triangle's record, then its vertices).  The first pass therefore copies every
+// sample without candidates and lists the others (AaList, one atomic per
+// wave on one of many counters); the second pass evaluates only the listed
+// samples, so no wave of the first waits for them.
+
+// The smoothed value of sample p (all of its candidate pairs evaluated).
 template <bool LIGHT, int C>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void aa_forward_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
+__device__ __forceinline__ void aa_forward_sample(const ViewConst &v, long long base, const TriSetup *__restrict__ setup,
+                                                  const int *__restrict__ faces, const unsigned char *__restrict__ silm,
+                                                  const float *__restrict__ verts,
+                                                  const unsigned long long *__restrict__ kv,
+                                                  const float *__restrict__ src, float *__restrict__ dst, int p) {
+    const int W = v.W;
+    const long long cstride = LIGHT ? (long long)W * v.H : 1;
+    const int pstride = LIGHT ? 1 : C;
+    const int i = p % W, j = p / W;
+    const unsigned long long ks = kv[p];
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) acc[c] = src[base + (long long)p * pstride + c * cstride];
+    const float self[3] = {acc[0], acc[1], acc[2]};
+    const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+    const AANeighbours nb = aa_neighbours(v, kv, silm, ks, i, j);
+    // values of the candidate neighbours, fetched before the pair tests
+    // so that they arrive with the triangle records
+    float nv[4][3];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            nv[d][c] = (nb.cand[d] && c < C) ? src[base + (long long)nb.q[d] * pstride + c * cstride] : 0.f;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        if (!nb.cand[d]) continue;
+        const int in_ = i + di[d], jn = j + dj[d];
+        const unsigned long long kn = nb.kn[d];
+        bool self_front;
+        AAPair pr;
+        if (!aa_eval<false>(v, setup, faces, silm, verts, ks, kn, i, j, in_, jn, d < 2, self_front, pr)) continue;
+        const bool self_recv = (pr.recv == 1) != self_front;   // receiver: other when recv==1
+        if (!self_recv) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (c < C) acc[c] += pr.w * (nv[d][c] - self[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) dst[base + (long long)p * pstride + c * cstride] = acc[c];
+}
+
+// First pass: copy samples without candidates, list the others.
+template <bool LIGHT, int C>
+__global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__restrict__ views,
+                                                         const RenderConst *__restrict__ renders,
+                                                         const unsigned char *__restrict__ silm,
+                                                         const unsigned long long *__restrict__ keys,
+                                                         const float *__restrict__ src, float *__restrict__ dst,
+                                                         AaList list) {
+    const Blk blk = xcd_block2();
+    const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
+    const int W = v.W, H = v.H;
+    const int p = blk.x * blockDim.x + threadIdx.x;
+    if (p >= W * H) return;
+    const long long base = LIGHT ? v.map_off : renders[blk.y].img_off;
+    const long long cstride = LIGHT ? (long long)W * H : 1;
+    const int pstride = LIGHT ? 1 : C;
+    const unsigned long long *kv = keys + v.pix_off;
+    float val[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) val[c] = src[base + (long long)p * pstride + c * cstride];
+    bool cand = false;
+    if (v.antialias && v.nfaces > 0) {
+        const AANeighbours nb = aa_neighbours(v, kv, silm, kv[p], p % W, p / W);
+        cand = nb.cand[0] || nb.cand[1] || nb.cand[2] || nb.cand[3];
+    }
+    wave_append(cand, make_uint2((unsigned)blk.y, (unsigned)p), list, (long long)blk.y * gridDim.x + blk.x);
+    if (cand) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < C) dst[base + (long long)p * pstride + c * cstride] = val[c];
+}
+
+// One pass over every sample (camera images: their candidates are too
+// frequent for a second pass to pay off).
+template <bool LIGHT, int C>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void aa_forward_direct_kernel(const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders,
                                   const TriSetup *__restrict__ setup, const int *__restrict__ faces,
                                   const unsigned char *__restrict__ silm, const float *__restrict__ verts,
                                   const unsigned long long *__restrict__ keys, const float *__restrict__ src,
@@ -142,6 +232,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         if (c < C) dst[base + (long long)p * pstride + c * cstride] = acc[c];
+}
+
+// Second pass: one workgroup per list segment.
+template <bool LIGHT, int C>
+__global__ __launch_bounds__(256) void aa_forward_list_kernel(
+    const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders, const TriSetup *__restrict__ setup,
+    const int *__restrict__ faces, const unsigned char *__restrict__ silm, const float *__restrict__ verts,
+    const unsigned long long *__restrict__ keys, const float *__restrict__ src, float *__restrict__ dst,
+    AaList list) {
+    const unsigned seg = blockIdx.x, n = list.counts[seg];
+    for (unsigned e = threadIdx.x; e < n; e += blockDim.x) {
+        const uint2 it = list.items[(size_t)seg * list.segcap + e];
+        const ViewConst &v = LIGHT ? views[it.x] : views[renders[it.x].camera_view];
+        const long long base = LIGHT ? v.map_off : renders[it.x].img_off;
+        aa_forward_sample<LIGHT, C>(v, base, setup, faces, silm, verts, keys + v.pix_off, src, dst, (int)it.y);
+    }
 }
 
 // ----------------------------------------------------------------------------- lookup + shade
@@ -305,18 +411,29 @@ hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const T
 
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
                              const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
-                             const unsigned long long *keys, const float *src, float *dst, int C, hipStream_t s) {
+                             const unsigned long long *keys, const float *src, float *dst, int C, uint2 *list,
+                             unsigned *counts, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const dim3 grid((max_pix + 255) / 256, n);
-    if (light)
-        hipLaunchKernelGGL((aa_forward_kernel<true, 2>), grid, dim3(256), 0, s, views, renders, setup, faces, silm,
-                           verts, keys, src, dst);
-    else if (C == 1)
-        hipLaunchKernelGGL((aa_forward_kernel<false, 1>), grid, dim3(256), 0, s, views, renders, setup, faces, silm,
-                           verts, keys, src, dst);
-    else
-        hipLaunchKernelGGL((aa_forward_kernel<false, 3>), grid, dim3(256), 0, s, views, renders, setup, faces, silm,
-                           verts, keys, src, dst);
+    const AaList l = aa_list_for(list, counts, (long long)grid.x * grid.y);
+#define DSM_AAF(LL, CC)                                                                                          \
+    do {                                                                                                         \
+        hipLaunchKernelGGL((aa_forward_kernel<LL, CC>), grid, dim3(256), 0, s, views, renders, silm, keys, src,  \
+                           dst, l);                                                                              \
+        hipLaunchKernelGGL((aa_forward_list_kernel<LL, CC>), dim3(l.nseg), dim3(256), 0, s, views, renders,      \
+                           setup, faces, silm, verts, keys, src, dst, l);                                        \
+    } while (0)
+    // light maps in two passes (a sample with candidate pairs is rare there); camera images in one
+    if (light) {
+        DSM_AAF(true, 2);
+    } else if (C == 1) {
+        hipLaunchKernelGGL((aa_forward_direct_kernel<false, 1>), grid, dim3(256), 0, s, views, renders, setup, faces,
+                           silm, verts, keys, src, dst);
+    } else {
+        hipLaunchKernelGGL((aa_forward_direct_kernel<false, 3>), grid, dim3(256), 0, s, views, renders, setup, faces,
+                           silm, verts, keys, src, dst);
+    }
+#undef DSM_AAF
     return hipGetLastError();
 }
 
