@@ -1150,12 +1150,35 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
         for (int k = 0; k < 3; ++k) x[k] = verts[3 * (size_t)gv_idx + k];
     float gv[3] = {0, 0, 0};
     const int c0 = in ? vc_off[gv_idx] : 0, c1 = in ? vc_off[gv_idx + 1] : 0;
+    // the first eight corners' indices, loaded once for every view (a vertex
+    // of a closed mesh has about six)
+    constexpr int kHeld = 8;
+    int eh[kHeld];
+#pragma unroll
+    for (int k = 0; k < kHeld; ++k) eh[k] = c0 + k < c1 ? vc_list[c0 + k] : -1;
     for (int s = scene_views_off[b]; s < scene_views_off[b + 1]; ++s) {
         const int vi = scene_views[s];
         const ViewConst &v = views[vi];
         float gc[3] = {0, 0, 0};
-        // corners four at a time, so that four record loads are in flight
-        for (int c = c0; c < c1; c += 4) {
+        {
+            // the held corners' records: eight loads in flight
+            float4 a[kHeld];
+            float2 bb[kHeld];
+#pragma unroll
+            for (int k = 0; k < kHeld; ++k) {
+                // the corner's record: world x y z, clip x | clip y w
+                const float *rec = gtri + (size_t)(v.setup_off + (max(eh[k], 0) >> 2)) * kGtriStride + (eh[k] & 3) * 8;
+                a[k] = eh[k] >= 0 ? *(const float4 *)rec : make_float4(0.f, 0.f, 0.f, 0.f);
+                bb[k] = eh[k] >= 0 ? *(const float2 *)(rec + 4) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int k = 0; k < kHeld; ++k) {
+                gv[0] += a[k].x; gv[1] += a[k].y; gv[2] += a[k].z;
+                gc[0] += a[k].w; gc[1] += bb[k].x; gc[2] += bb[k].y;
+            }
+        }
+        // further corners four at a time
+        for (int c = c0 + kHeld; c < c1; c += 4) {
             int e[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) e[k] = c + k < c1 ? vc_list[c + k] : -1;
