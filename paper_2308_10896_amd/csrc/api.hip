@@ -503,6 +503,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sv_bin_pair = o; o = align_up(o + 4 * (size_t)p->capacity);
     p->sv_overflow = o; o = align_up(o + 4 * ((size_t)tri + 1));
     p->sv_zc = o; o = align_up(o + 4 * (size_t)std::max(L, 1));
+    p->sv_aa_flag = o; o = align_up(o + (size_t)pix);        // per sample: it has candidate smoothing pairs
     p->saved_bytes = std::max<size_t>(o, kAlign);
     // scratch layout
     o = 0;
@@ -691,6 +692,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     unsigned *overflow = at<unsigned>(saved, p->sv_overflow);
     float *F1 = at<float>(scratch, p->sc_F1);
     unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
+    unsigned char *aa_flag = at<unsigned char>(saved, p->sv_aa_flag);
     float4 *clip = at<float4>(saved, p->sv_clip);
     TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
     unsigned char *silm = at<unsigned char>(saved, p->sv_sil);
@@ -721,7 +723,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_TRY(launch_resolve(p->views_d, p->L, p->max_light_texels, tv, keys, F0, s));
     DSM_MARK(DSM_STAGE_LIGHT_AA);
     DSM_TRY(launch_aa_forward(true, p->views_d, p->renders_d, p->L, p->max_light_texels, setup, p->faces_d, silm,
-                              verts, keys, F0, F1, 2, aa_list, aa_count, s));
+                              verts, keys, F0, F1, 2, aa_list, aa_count, aa_flag, s));
     DSM_MARK(DSM_STAGE_FILTER);
     if (p->has_cube) DSM_TRY(launch_cube_pad(p->views_d, p->L, p->max_cube_padded, p->cube_taps_d, F1, s));
     for (const auto &g : p->blur_groups)
@@ -731,7 +733,7 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
                           img0, p->C, s));
     DSM_MARK(DSM_STAGE_CAMERA_AA);
     DSM_TRY(launch_aa_forward(false, p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
-                              verts, keys, img0, images, p->C, nullptr, nullptr, s));
+                              verts, keys, img0, images, p->C, nullptr, nullptr, aa_flag, s));
     return DSM_OK;
 }
 
@@ -739,6 +741,7 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
                             const void *saved, void *scratch, const float *gimg, float *gverts, float *glparams,
                             float *galbedo, hipStream_t s, const StageMarks *marks = nullptr) {
     const unsigned long long *keys = at<unsigned long long>(saved, p->sv_keys);
+    const unsigned char *aa_flag = at<unsigned char>(saved, p->sv_aa_flag);
     const float4 *clip = at<float4>(saved, p->sv_clip);
     const TriSetup *setup = at<TriSetup>(saved, p->sv_setup);
     const unsigned char *silm = at<unsigned char>(saved, p->sv_sil);
@@ -775,7 +778,7 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, jac, nullptr, s));
     DSM_MARK(DSM_STAGE_CAMERA_AA_ADJ);
     DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
-                                      verts, keys, img0, gimg, gimg0, gclip, p->C, s));
+                                      verts, keys, aa_flag, img0, gimg, gimg0, gclip, p->C, s));
     DSM_MARK(DSM_STAGE_LOOKUP_ADJ);
     DSM_TRY(launch_lookup_backward(p->tile, p->views_d, p->L, p->Cm, p->max_cam_tiles, p->max_lights_per_render,
                                    p->renders_d, p->cam_renders_off_d, p->cam_renders_d, p->render_lights_d,
@@ -790,8 +793,8 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
                                           gF1, s));
     DSM_MARK(DSM_STAGE_LIGHT_ADJ);
     DSM_TRY(launch_light_backward(p->tile, p->views_d, p->L, p->max_light_tiles, setup, p->faces_d, silm, verts,
-                                  tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,
-                                  part_light, jac, pair_off, p->capacity, s));
+                                  tv, keys, aa_flag, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums,
+                                  gtri, part_light, jac, pair_off, p->capacity, s));
     DSM_MARK(DSM_STAGE_VERTEX_GRAD);
     DSM_TRY(launch_vertex_gradients(p->views_d, p->L, p->B, p->max_scene_verts, p->max_scene_faces, p->ntri,
                                     p->capacity, p->scene_vert_off_d, p->scene_face_off_d, p->scene_views_off_d,

@@ -310,7 +310,7 @@ hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const T
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
                              const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
                              const unsigned long long *keys, const float *src, float *dst, int C, uint2 *list,
-                             unsigned *count, hipStream_t s);
+                             unsigned *count, unsigned char *aa_flag, hipStream_t s);
 hipError_t launch_lookup(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
                          const int *render_lights, const TriVerts *tv, const float *albedo,
                          const unsigned long long *keys, const float *maps, float *img0, int C, hipStream_t s);
@@ -320,8 +320,8 @@ hipError_t launch_tri_verts(const int *scene_vert_off, const int *scene_face_off
 // backward
 hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
                                      const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
-                                     const unsigned long long *keys, const float *img0, const float *gimg,
-                                     float *gimg0, float4 *gclip, int C, hipStream_t s);
+                                     const unsigned long long *keys, const unsigned char *aa_flag, const float *img0,
+                                     const float *gimg, float *gimg0, float4 *gclip, int C, hipStream_t s);
 hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int Cm, int max_tiles, int max_lights,
                                   const RenderConst *renders, const int *cam_renders_off, const int *cam_renders,
                                   const int *render_lights, const int *faces, const float *verts, const float *albedo,
@@ -332,7 +332,7 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
                                   const unsigned *pair_off, unsigned capacity, hipStream_t s);
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const unsigned char *silm, const float *verts, const TriVerts *tv,
-                                 const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
+                                 const unsigned long long *keys, const unsigned char *aa_flag, const float *F0, const float *gF1, float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
                                  const float *jac, const unsigned *pair_off, unsigned capacity, hipStream_t s);

@@ -109,7 +109,8 @@ template <int C>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void aa_camera_backward_kernel(
     const ViewConst *__restrict__ views, const RenderConst *__restrict__ renders, const TriSetup *__restrict__ setup,
     const int *__restrict__ faces, const unsigned char *__restrict__ silm, const float *__restrict__ verts,
-    const unsigned long long *__restrict__ keys, const float *__restrict__ img0, const float *__restrict__ gimg,
+    const unsigned long long *__restrict__ keys, const unsigned char *__restrict__ aa_flag,
+    const float *__restrict__ img0, const float *__restrict__ gimg,
     float *__restrict__ gimg0, float4 *__restrict__ gclip) {
     const Blk blk = xcd_block2();
     const RenderConst &R = renders[blk.y];
@@ -124,7 +125,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
     for (int c = 0; c < 3; ++c)
         if (c < C) acc[c] = g[(long long)p * C + c];
     const float gself[3] = {acc[0], acc[1], acc[2]};
-    if (v.antialias && v.nfaces > 0) {
+    // samples the forward found without candidate pairs pass the gradient through
+    if (v.antialias && v.nfaces > 0 && aa_flag[v.pix_off + p]) {
         const int i = p % W, j = p / W;
         const unsigned long long *kv = keys + v.pix_off;
         const unsigned long long ks = kv[p];
@@ -933,8 +935,8 @@ template <int T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void light_backward_kernel(
     const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup, const int *__restrict__ faces,
     const unsigned char *__restrict__ silm, const float *__restrict__ verts, const TriVerts *__restrict__ tv,
-    const unsigned long long *__restrict__ keys, const float *__restrict__ F0, const float *__restrict__ gF1,
-    float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
+    const unsigned long long *__restrict__ keys, const unsigned char *__restrict__ aa_flag,
+    const float *__restrict__ F0, const float *__restrict__ gF1, float4 *__restrict__ gclip, const unsigned *__restrict__ tile_start, const unsigned *__restrict__ bins,
     const unsigned *__restrict__ bin_pair, unsigned char *__restrict__ pair_flag, float *__restrict__ pair_sums,
     float *__restrict__ gtri, float *__restrict__ part_light, const float *__restrict__ jac,
     const unsigned *__restrict__ pair_off, unsigned capacity) {
@@ -971,7 +973,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void l
 #pragma unroll
         for (int q = 0; q < 18; ++q) val[k][q] = 0.f;
         float g0 = in ? ga[pp] : 0.f, g1 = in ? gbp[pp] : 0.f;
-        if (in && l.antialias && l.nfaces > 0) {
+        // texels the forward found without candidate pairs skip the smoothing terms
+        if (in && l.antialias && l.nfaces > 0 && aa_flag[l.pix_off + pp]) {
             const float gs0 = g0, gs1 = g1;
             const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
             // the four neighbour keys, then their silhouette bytes, each batch
@@ -1397,16 +1400,16 @@ __global__ __launch_bounds__(256) void pose_backward_kernel(const int *__restric
 
 hipError_t launch_aa_camera_backward(const ViewConst *views, const RenderConst *renders, int R, int max_pix,
                                      const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
-                                     const unsigned long long *keys, const float *img0, const float *gimg,
-                                     float *gimg0, float4 *gclip, int C, hipStream_t s) {
+                                     const unsigned long long *keys, const unsigned char *aa_flag, const float *img0,
+                                     const float *gimg, float *gimg0, float4 *gclip, int C, hipStream_t s) {
     if (R == 0) return hipSuccess;
     const dim3 grid((max_pix + 255) / 256, R);
     if (C == 1)
         hipLaunchKernelGGL(aa_camera_backward_kernel<1>, grid, dim3(256), 0, s, views, renders, setup, faces, silm,
-                           verts, keys, img0, gimg, gimg0, gclip);
+                           verts, keys, aa_flag, img0, gimg, gimg0, gclip);
     else
         hipLaunchKernelGGL(aa_camera_backward_kernel<3>, grid, dim3(256), 0, s, views, renders, setup, faces, silm,
-                           verts, keys, img0, gimg, gimg0, gclip);
+                           verts, keys, aa_flag, img0, gimg, gimg0, gclip);
     return hipGetLastError();
 }
 
@@ -1446,7 +1449,8 @@ hipError_t launch_lookup_backward(int tile, const ViewConst *views, int L, int C
 
 hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int max_tiles, const TriSetup *setup,
                                  const int *faces, const unsigned char *silm, const float *verts, const TriVerts *tv,
-                                 const unsigned long long *keys, const float *F0, const float *gF1, float4 *gclip,
+                                 const unsigned long long *keys, const unsigned char *aa_flag, const float *F0, const float *gF1,
+                                 float4 *gclip,
                                  const unsigned *tile_start, const unsigned *bins, const unsigned *bin_pair,
                                  unsigned char *pair_flag, float *pair_sums, float *gtri, float *part_light,
                                  const float *jac, const unsigned *pair_off, unsigned capacity, hipStream_t s) {
@@ -1454,8 +1458,8 @@ hipError_t launch_light_backward(int tile, const ViewConst *views, int L, int ma
     const dim3 grid(max_tiles, L);
 #define DSM_LIB(TT)                                                                                                  \
     hipLaunchKernelGGL((light_backward_kernel<TT>), grid, dim3(TileShape<TT>::NT), 0, s, views, setup, faces, silm,  \
-                       verts, tv, keys, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, gtri,     \
-                       part_light, jac, pair_off, capacity)
+                       verts, tv, keys, aa_flag, F0, gF1, gclip, tile_start, bins, bin_pair, pair_flag, pair_sums, \
+                       gtri, part_light, jac, pair_off, capacity)
     if (tile == 8) DSM_LIB(8);
     else if (tile == 16) DSM_LIB(16);
     else DSM_LIB(32);

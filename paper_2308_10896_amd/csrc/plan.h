@@ -64,7 +64,7 @@ struct dsm_plan {
     // layout of the caller's saved buffer (byte offsets): everything the
     // forward writes and the backward reads, the binning state included
     size_t sv_counters = 0, sv_zero_end = 0, sv_keys = 0, sv_clip = 0, sv_setup = 0, sv_sil = 0, sv_tv = 0, sv_F0 = 0,
-           sv_M = 0, sv_img0 = 0, sv_pair_off = 0, sv_tile_start = 0, sv_bins = 0, sv_bin_pair = 0, sv_overflow = 0, sv_zc = 0,
+           sv_M = 0, sv_img0 = 0, sv_pair_off = 0, sv_tile_start = 0, sv_bins = 0, sv_bin_pair = 0, sv_overflow = 0, sv_zc = 0, sv_aa_flag = 0,
            saved_bytes = 0;
     // layout of the caller's scratch buffer (byte offsets): temporaries of
     // one call, nothing carried from a forward to its backward

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__rest
                                                          const unsigned char *__restrict__ silm,
                                                          const unsigned long long *__restrict__ keys,
                                                          const float *__restrict__ src, float *__restrict__ dst,
-                                                         AaList list) {
+                                                         AaList list, unsigned char *__restrict__ flag) {
     const Blk blk = xcd_block2();
     const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
     const int W = v.W, H = v.H;
@@ -172,6 +172,7 @@ __global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__rest
         const AANeighbours nb = aa_neighbours(v, kv, silm, kv[p], p % W, p / W);
         cand = nb.cand[0] || nb.cand[1] || nb.cand[2] || nb.cand[3];
     }
+    flag[v.pix_off + p] = cand ? 1 : 0;
     wave_append(cand, make_uint2((unsigned)blk.y, (unsigned)p), list, (long long)blk.y * gridDim.x + blk.x);
     if (cand) return;
 #pragma unroll
@@ -186,7 +187,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
                                   const TriSetup *__restrict__ setup, const int *__restrict__ faces,
                                   const unsigned char *__restrict__ silm, const float *__restrict__ verts,
                                   const unsigned long long *__restrict__ keys, const float *__restrict__ src,
-                                  float *__restrict__ dst) {
+                                  float *__restrict__ dst,
+                                  unsigned char *__restrict__ flag) {
     const Blk blk = xcd_block2();
     const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
     const int W = v.W, H = v.H;
@@ -204,8 +206,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
         if (c < C) acc[c] = src[base + (long long)p * pstride + c * cstride];
     const float self[3] = {acc[0], acc[1], acc[2]};
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+    bool any = false;
     if (v.antialias && v.nfaces > 0) {
         const AANeighbours nb = aa_neighbours(v, kv, silm, ks, i, j);
+        any = nb.cand[0] || nb.cand[1] || nb.cand[2] || nb.cand[3];
         // values of the candidate neighbours, fetched before the pair tests
         // so that they arrive with the triangle records
         float nv[4][3];
@@ -229,6 +233,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
                 if (c < C) acc[c] += pr.w * (nv[d][c] - self[c]);
         }
     }
+    flag[v.pix_off + p] = any ? 1 : 0;      // for the adjoint: this sample has candidate pairs
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         if (c < C) dst[base + (long long)p * pstride + c * cstride] = acc[c];
@@ -412,14 +417,14 @@ hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const T
 hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderConst *renders, int n, int max_pix,
                              const TriSetup *setup, const int *faces, const unsigned char *silm, const float *verts,
                              const unsigned long long *keys, const float *src, float *dst, int C, uint2 *list,
-                             unsigned *counts, hipStream_t s) {
+                             unsigned *counts, unsigned char *aa_flag, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const dim3 grid((max_pix + 255) / 256, n);
     const AaList l = aa_list_for(list, counts, (long long)grid.x * grid.y);
 #define DSM_AAF(LL, CC)                                                                                          \
     do {                                                                                                         \
         hipLaunchKernelGGL((aa_forward_kernel<LL, CC>), grid, dim3(256), 0, s, views, renders, silm, keys, src,  \
-                           dst, l);                                                                              \
+                           dst, l, aa_flag);                                                                     \
         hipLaunchKernelGGL((aa_forward_list_kernel<LL, CC>), dim3(l.nseg), dim3(256), 0, s, views, renders,      \
                            setup, faces, silm, verts, keys, src, dst, l);                                        \
     } while (0)
@@ -428,10 +433,10 @@ hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderCon
         DSM_AAF(true, 2);
     } else if (C == 1) {
         hipLaunchKernelGGL((aa_forward_direct_kernel<false, 1>), grid, dim3(256), 0, s, views, renders, setup, faces,
-                           silm, verts, keys, src, dst);
+                           silm, verts, keys, src, dst, aa_flag);
     } else {
         hipLaunchKernelGGL((aa_forward_direct_kernel<false, 3>), grid, dim3(256), 0, s, views, renders, setup, faces,
-                           silm, verts, keys, src, dst);
+                           silm, verts, keys, src, dst, aa_flag);
     }
 #undef DSM_AAF
     return hipGetLastError();
