@@ -59,13 +59,14 @@ __device__ __forceinline__ void wave_add(const float (&val)[N], float *dst) {
     }
 }
 
-__device__ __forceinline__ float ndc_c(int i, int n) { return (float)(2 * i + 1) / (float)n - 1.0f; }
-
-// Reciprocal (about one ulp) for quotients that only scale a gradient term:
-// the correctly rounded division the rest of the library uses (for the
-// quantities that decide coverage, cells and branches) costs about ten
-// instructions, this one.
+// Reciprocal (about one ulp) for quotients that decide no coverage, cell or
+// index (gradient terms, and the shading values the adjoints recompute exactly
+// as the forward kernels form them): the correctly rounded division the
+// raster setup needs costs about ten instructions, this one.
 __device__ __forceinline__ float grcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// NDC of pixel centre i of n, as the forward resolve and lookup form it.
+__device__ __forceinline__ float ndc_c(int i, int n) { return (float)(2 * i + 1) * grcp((float)n) - 1.0f; }
 
 // Barycentrics through the hardware reciprocal of their sum (about one ulp):
 // the forward lookup forms the world point the same way, so the reverse pass
@@ -513,8 +514,7 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
     const float e1x = v1[0] - v0[0], e1y = v1[1] - v0[1], e1z = v1[2] - v0[2];
     const float e2x = v2[0] - v0[0], e2y = v2[1] - v0[1], e2z = v2[2] - v0[2];
     const float crx = e1y * e2z - e1z * e2y, cry = e1z * e2x - e1x * e2z, crz = e1x * e2y - e1y * e2x;
-    const float nn = sqrtf((crx * crx + cry * cry) + crz * crz);
-    const float rn0 = __builtin_amdgcn_rcpf(nn);
+    const float rn0 = __builtin_amdgcn_rsqf((crx * crx + cry * cry) + crz * crz);
     const float nx = crx * rn0, ny = cry * rn0, nz = crz * rn0;
     float rho[3] = {0.f, 0.f, 0.f};
     for (int c = 0; c < C; ++c) rho[c] = c == 0 ? r.c.y : c == 1 ? r.c.z : r.c.w;   // from the face record
@@ -572,11 +572,11 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
                 const float ddx = x - l.pos[0], ddy = y - l.pos[1], ddz = z - l.pos[2];
                 depth = sqrtf((ddx * ddx + ddy * ddy) + ddz * ddz);
             }
-            zz = depth / l.zfar - l.zc;
+            zz = depth * grcp(l.zfar) - l.zc;
             warp_receiver(l, zz, zw, floor_v);
             var = fmaxf(m2 - m1 * m1, floor_v);
             dd = zw - m1;
-            visr = (zw <= m1) ? 1.f : var / (var + dd * dd);
+            visr = (zw <= m1) ? 1.f : var * grcp(var + dd * dd);
             vis = bleed_reduce(l, visr);
         }
         float ox, oy, oz, olen = 1.f;
@@ -585,7 +585,8 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
         } else {
             ox = l.pos[0] - x; oy = l.pos[1] - y; oz = l.pos[2] - z;
             olen = sqrtf((ox * ox + oy * oy) + oz * oz);
-            ox /= olen; oy /= olen; oz /= olen;
+            const float rol = grcp(olen);
+            ox *= rol; oy *= rol; oz *= rol;
         }
         const float ndo = (nx * ox + ny * oy) + nz * oz;
         const float lam = fmaxf(ndo, 0.f);
@@ -713,7 +714,7 @@ __device__ __forceinline__ void lookup_pixel_grad(const ViewConst &cv, const Ren
     for (int c = 0; c < 3; ++c) vals[18 + c] = c < C ? g[c] * shade : 0.f;
     // normal: n = cr / |cr|, cr = e1 x e2
     const float ndg = fmaf(nz, gn[2], fmaf(ny, gn[1], nx * gn[0]));
-    const float rn = grcp(nn);
+    const float rn = rn0;
     const float gcr[3] = {fmaf(-nx, ndg, gn[0]) * rn, fmaf(-ny, ndg, gn[1]) * rn, fmaf(-nz, ndg, gn[2]) * rn};
     const float ge1[3] = {fmaf(e2y, gcr[2], -e2z * gcr[1]), fmaf(e2z, gcr[0], -e2x * gcr[2]),
                           fmaf(e2x, gcr[1], -e2y * gcr[0])};

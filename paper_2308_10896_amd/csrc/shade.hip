@@ -43,7 +43,12 @@ __device__ __forceinline__ Bary persp_bary_rcp(float4 c0, float4 c1, float4 c2, 
     return Bary{k0 * rs, k1 * rs, k2 * rs};
 }
 
-__device__ __forceinline__ float ndc_centre(int i, int n) { return (float)(2 * i + 1) / (float)n - 1.0f; }
+// The shading and resolve arithmetic below decides no coverage or index, so
+// its quotients go through the hardware reciprocal (about 1 ulp) instead of
+// the correctly rounded division the raster setup needs.
+__device__ __forceinline__ float ndc_centre(int i, int n) {
+    return (float)(2 * i + 1) * __builtin_amdgcn_rcpf((float)n) - 1.0f;
+}
 
 __device__ __forceinline__ float light_depth(const ViewConst &l, float x, float y, float z) {
     float d;
@@ -53,7 +58,7 @@ __device__ __forceinline__ float light_depth(const ViewConst &l, float x, float 
         const float dx = x - l.pos[0], dy = y - l.pos[1], dz = z - l.pos[2];
         d = sqrtf((dx * dx + dy * dy) + dz * dz);
     }
-    return d / l.zfar - l.zc;
+    return d * __builtin_amdgcn_rcpf(l.zfar) - l.zc;
 }
 
 // ----------------------------------------------------------------------------- resolve
@@ -305,8 +310,7 @@ __global__ __launch_bounds__(256) void lookup_kernel(const ViewConst *__restrict
         const float e1x = v1[0] - v0[0], e1y = v1[1] - v0[1], e1z = v1[2] - v0[2];
         const float e2x = v2[0] - v0[0], e2y = v2[1] - v0[1], e2z = v2[2] - v0[2];
         float cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
-        const float nn = sqrtf((cx * cx + cy * cy) + cz * cz);
-        const float rn = __builtin_amdgcn_rcpf(nn);
+        const float rn = __builtin_amdgcn_rsqf((cx * cx + cy * cy) + cz * cz);
         nx[k] = cx * rn;
         ny[k] = cy * rn;
         nz[k] = cz * rn;
@@ -369,7 +373,7 @@ __global__ __launch_bounds__(256) void lookup_kernel(const ViewConst *__restrict
                 warp_receiver(l, light_depth(l, x[k], y[k], z[k]), zw, floor_v);
                 const float var = fmaxf(m2 - m1 * m1, floor_v);
                 const float dd = zw - m1;
-                vis = bleed_reduce(l, (zw <= m1) ? 1.f : var / (var + dd * dd));
+                vis = bleed_reduce(l, (zw <= m1) ? 1.f : var * __builtin_amdgcn_rcpf(var + dd * dd));
             }
             float ox, oy, oz;
             if (l.kind == kDirectional) {
@@ -380,10 +384,10 @@ __global__ __launch_bounds__(256) void lookup_kernel(const ViewConst *__restrict
                 ox = l.pos[0] - x[k];
                 oy = l.pos[1] - y[k];
                 oz = l.pos[2] - z[k];
-                const float on = sqrtf((ox * ox + oy * oy) + oz * oz);
-                ox /= on;
-                oy /= on;
-                oz /= on;
+                const float ron = __builtin_amdgcn_rsqf((ox * ox + oy * oy) + oz * oz);
+                ox *= ron;
+                oy *= ron;
+                oz *= ron;
             }
             const float lam = fmaxf((nx[k] * ox + ny[k] * oy) + nz[k] * oz, 0.f);
             float cone = 1.f;
