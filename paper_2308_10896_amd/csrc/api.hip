@@ -525,6 +525,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_pair_flag = o; o = align_up(o + (size_t)p->capacity);
     p->sc_gimg0 = o; o = align_up(o + 4 * (size_t)img);
     p->sc_bigcount = o; o = align_up(o + 64);
+    p->sc_zero_rec = o; o = align_up(o + 32);          // an all-zero corner record for the vertex gather
     p->sc_gM = o; o = align_up(o + 4 * (size_t)fmaps);
     p->sc_gclip = o; o = align_up(o + 16 * (size_t)clip);
     p->sc_zero_bwd_end = o;
@@ -799,7 +800,7 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     DSM_TRY(launch_vertex_gradients(p->views_d, p->L, p->B, p->max_scene_verts, p->max_scene_faces, p->ntri,
                                     p->capacity, p->scene_vert_off_d, p->scene_face_off_d, p->scene_views_off_d,
                                     p->scene_views_d, p->vc_off_d, p->vc_list_d, pair_off, pair_flag, pair_sums, gtri,
-                                    big_list,
+                                    at<float>(scratch, p->sc_zero_rec), big_list,
                                     big_count, verts, gclip, gverts, part_gm, galbedo, p->C, jac, s));
     DSM_MARK(DSM_STAGE_LIGHT_GRAD);
     DSM_TRY(launch_glight_reduce(p->views_d, p->L, p->renders_d, p->light_renders_off_d, p->light_renders_d, part_gm,

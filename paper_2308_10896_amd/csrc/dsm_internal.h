@@ -340,7 +340,7 @@ hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max
                                    unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
                                    const int *scene_views_off, const int *scene_views, const int *vc_off,
                                    const int *vc_list, const unsigned *pair_off, const unsigned char *pair_flag,
-                                   const float *pair_sums, float *gtri,
+                                   const float *pair_sums, float *gtri, const float *zero_rec,
                                    unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
                                    float *gverts, float *part_gm, float *galbedo, int C, const float *jac, hipStream_t s);
 hipError_t launch_overflow_rows_zero(const unsigned *list, const DevCounters *counters, float *gtri, hipStream_t s);

@@ -1141,8 +1141,8 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
     const ViewConst *__restrict__ views, int L, const int *__restrict__ scene_vert_off,
     const int *__restrict__ scene_views_off, const int *__restrict__ scene_views, const int *__restrict__ vc_off,
     const int *__restrict__ vc_list, const float *__restrict__ verts, const float *__restrict__ gtri,
-    const float4 *__restrict__ gclip, float *__restrict__ gverts, float *__restrict__ part_gm,
-    const float *__restrict__ jac) {
+    const float *__restrict__ zero_rec, const float4 *__restrict__ gclip, float *__restrict__ gverts,
+    float *__restrict__ part_gm, const float *__restrict__ jac) {
     const int b = blockIdx.y;
     const int nv = scene_vert_off[b + 1] - scene_vert_off[b];
     if ((int)(blockIdx.x * blockDim.x) >= nv) return;        // whole workgroup
@@ -1163,7 +1163,19 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
     for (int s = scene_views_off[b]; s < scene_views_off[b + 1]; ++s) {
         const int vi = scene_views[s];
         const ViewConst &v = views[vi];
+        const int soff = v.setup_off;
         float gc[3] = {0, 0, 0};
+        // Every slot loads a record, absent corners an all-zero one
+        // (zero_rec), so that no load sits behind a branch and the sums add
+        // the same terms in the same order.  Corners past the held ones go
+        // sixteen at a time, the next sixteen indices loaded with the current
+        // records: a vertex of high valence (the pole of a UV sphere has one
+        // corner per longitude) waits for one load per sixteen corners.
+        constexpr int kChunk = 16;
+        const float4 ga = gclip[v.clip_off + (in ? vl : 0)];     // silhouette terms, issued early
+        int e[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) e[k] = c0 + kHeld + k < c1 ? vc_list[c0 + kHeld + k] : -1;
         {
             // the held corners' records: eight loads in flight
             float4 a[kHeld];
@@ -1171,9 +1183,10 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
 #pragma unroll
             for (int k = 0; k < kHeld; ++k) {
                 // the corner's record: world x y z, clip x | clip y w
-                const float *rec = gtri + (size_t)(v.setup_off + (max(eh[k], 0) >> 2)) * kGtriStride + (eh[k] & 3) * 8;
-                a[k] = eh[k] >= 0 ? *(const float4 *)rec : make_float4(0.f, 0.f, 0.f, 0.f);
-                bb[k] = eh[k] >= 0 ? *(const float2 *)(rec + 4) : make_float2(0.f, 0.f);
+                const float *rec =
+                    eh[k] >= 0 ? gtri + (size_t)(soff + (eh[k] >> 2)) * kGtriStride + (eh[k] & 3) * 8 : zero_rec;
+                a[k] = *(const float4 *)rec;
+                bb[k] = *(const float2 *)(rec + 4);
             }
 #pragma unroll
             for (int k = 0; k < kHeld; ++k) {
@@ -1181,28 +1194,25 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
                 gc[0] += a[k].w; gc[1] += bb[k].x; gc[2] += bb[k].y;
             }
         }
-        // further corners four at a time
-        for (int c = c0 + kHeld; c < c1; c += 4) {
-            int e[4];
+        for (int c = c0 + kHeld; c < c1; c += kChunk) {
+            float4 a[kChunk];
+            float2 b[kChunk];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) e[k] = c + k < c1 ? vc_list[c + k] : -1;
-            float4 a[4];
-            float2 b[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                // the corner's record: world x y z, clip x | clip y w
-                const float *rec = gtri + (size_t)(v.setup_off + (max(e[k], 0) >> 2)) * kGtriStride + (e[k] & 3) * 8;
-                a[k] = e[k] >= 0 ? *(const float4 *)rec : make_float4(0.f, 0.f, 0.f, 0.f);
-                b[k] = e[k] >= 0 ? *(const float2 *)(rec + 4) : make_float2(0.f, 0.f);
+            for (int k = 0; k < kChunk; ++k) {
+                const float *rec =
+                    e[k] >= 0 ? gtri + (size_t)(soff + (e[k] >> 2)) * kGtriStride + (e[k] & 3) * 8 : zero_rec;
+                a[k] = *(const float4 *)rec;
+                b[k] = *(const float2 *)(rec + 4);
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < kChunk; ++k) e[k] = c + kChunk + k < c1 ? vc_list[c + kChunk + k] : -1;
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) {
                 gv[0] += a[k].x; gv[1] += a[k].y; gv[2] += a[k].z;
                 gc[0] += a[k].w; gc[1] += b[k].x; gc[2] += b[k].y;
             }
         }
         if (in) {
-            const float4 ga = gclip[v.clip_off + vl];
             gc[0] += ga.x; gc[1] += ga.y; gc[2] += ga.w;
         }
         const float *M = v.M;
@@ -1472,7 +1482,7 @@ hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max
                                    unsigned capacity, const int *scene_vert_off, const int *scene_face_off,
                                    const int *scene_views_off, const int *scene_views, const int *vc_off,
                                    const int *vc_list, const unsigned *pair_off, const unsigned char *pair_flag,
-                                   const float *pair_sums, float *gtri,
+                                   const float *pair_sums, float *gtri, const float *zero_rec,
                                    unsigned *big_list, unsigned *big_count, const float *verts, const float4 *gclip,
                                    float *gverts, float *part_gm, float *galbedo, int C, const float *jac, hipStream_t s) {
     if (ntri > 0) {
@@ -1484,8 +1494,8 @@ hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max
     }
     if (max_verts > 0)
         hipLaunchKernelGGL(vertex_gather_kernel, dim3((max_verts + 255) / 256, B), dim3(256), 0, s, views, L,
-                           scene_vert_off, scene_views_off, scene_views, vc_off, vc_list, verts, gtri, gclip, gverts,
-                           part_gm, jac);
+                           scene_vert_off, scene_views_off, scene_views, vc_off, vc_list, verts, gtri, zero_rec, gclip,
+                           gverts, part_gm, jac);
     if (galbedo && max_faces > 0)
         hipLaunchKernelGGL(albedo_gather_kernel, dim3((max_faces + 255) / 256, B), dim3(256), 0, s, views, L,
                            scene_face_off, scene_views_off, scene_views, gtri, galbedo, C);
