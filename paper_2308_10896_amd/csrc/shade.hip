@@ -63,32 +63,51 @@ __device__ __forceinline__ float light_depth(const ViewConst &l, float x, float 
 
 // ----------------------------------------------------------------------------- resolve
 
-__global__ void resolve_kernel(const ViewConst *__restrict__ views, const TriVerts *__restrict__ tv,
-                               const unsigned long long *__restrict__ keys, float *__restrict__ F0) {
+// Texels per thread of the resolve: both keys, then both face records, in
+// flight together (the chain key -> record -> store is the kernel's latency).
+constexpr int kResolvePerThread = 2;
+
+__global__ __launch_bounds__(256) void resolve_kernel(const ViewConst *__restrict__ views,
+                                                      const TriVerts *__restrict__ tv,
+                                                      const unsigned long long *__restrict__ keys,
+                                                      float *__restrict__ F0) {
+    constexpr int PPT = kResolvePerThread;
     const ViewConst &l = views[blockIdx.y];
-    const int S = l.W;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= S * S) return;
-    const unsigned long long key = keys[l.pix_off + t];
-    float z = 1.0f - l.zc, z2;          // background: the far plane
-    if (key != kBgKey) {
-        const int tri = (int)(unsigned)key;
-        const TriVerts r = tv[l.face_off + tri];
-        const float v0[3] = {r.a.x, r.a.y, r.a.z}, v1[3] = {r.a.w, r.b.x, r.b.y}, v2[3] = {r.b.z, r.b.w, r.c.x};
-        const int i = t % S, j = t / S;
-        const float px = ndc_centre(i, S), py = -ndc_centre(j, S);
-        const float4 c0 = clip_of(l.M, v0[0], v0[1], v0[2]), c1 = clip_of(l.M, v1[0], v1[1], v1[2]),
-                     c2 = clip_of(l.M, v2[0], v2[1], v2[2]);
-        const Bary b = persp_bary_rcp(c0, c1, c2, px, py);
-        const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
-        const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
-        const float zz = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
-        z = light_depth(l, x, y, zz);
+    const int S = l.W, P = S * S;
+    const int t0 = blockIdx.x * (256 * PPT) + (int)threadIdx.x;
+    if (t0 >= P) return;
+    unsigned long long key[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int t = t0 + 256 * k;
+        key[k] = t < P ? keys[l.pix_off + t] : kBgKey;
     }
-    if (l.warp_c > 0.f) z = expf(l.warp_c * z);     // exponential maps
-    z2 = z * z;
-    F0[l.map_off + t] = z;
-    F0[l.map_off + (long long)S * S + t] = z2;
+    TriVerts r[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (key[k] != kBgKey) r[k] = tv[l.face_off + (int)(unsigned)key[k]];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int t = t0 + 256 * k;
+        if (t >= P) break;
+        float z = 1.0f - l.zc;          // background: the far plane
+        if (key[k] != kBgKey) {
+            const float v0[3] = {r[k].a.x, r[k].a.y, r[k].a.z}, v1[3] = {r[k].a.w, r[k].b.x, r[k].b.y},
+                        v2[3] = {r[k].b.z, r[k].b.w, r[k].c.x};
+            const int i = t % S, j = t / S;
+            const float px = ndc_centre(i, S), py = -ndc_centre(j, S);
+            const float4 c0 = clip_of(l.M, v0[0], v0[1], v0[2]), c1 = clip_of(l.M, v1[0], v1[1], v1[2]),
+                         c2 = clip_of(l.M, v2[0], v2[1], v2[2]);
+            const Bary b = persp_bary_rcp(c0, c1, c2, px, py);
+            const float x = (b.b0 * v0[0] + b.b1 * v1[0]) + b.b2 * v2[0];
+            const float y = (b.b0 * v0[1] + b.b1 * v1[1]) + b.b2 * v2[1];
+            const float zz = (b.b0 * v0[2] + b.b1 * v1[2]) + b.b2 * v2[2];
+            z = light_depth(l, x, y, zz);
+        }
+        if (l.warp_c > 0.f) z = expf(l.warp_c * z);     // exponential maps
+        F0[l.map_off + t] = z;
+        F0[l.map_off + (long long)P + t] = z * z;
+    }
 }
 
 // ----------------------------------------------------------------------------- smoothing forward
@@ -414,7 +433,8 @@ __global__ __launch_bounds__(256) void lookup_kernel(const ViewConst *__restrict
 hipError_t launch_resolve(const ViewConst *views, int L, int max_texels, const TriVerts *tv,
                           const unsigned long long *keys, float *F0, hipStream_t s) {
     if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(resolve_kernel, dim3((max_texels + 255) / 256, L), dim3(256), 0, s, views, tv, keys, F0);
+    hipLaunchKernelGGL(resolve_kernel, dim3((max_texels + 256 * kResolvePerThread - 1) / (256 * kResolvePerThread), L),
+                       dim3(256), 0, s, views, tv, keys, F0);
     return hipGetLastError();
 }
 
