@@ -63,9 +63,10 @@ __device__ __forceinline__ float light_depth(const ViewConst &l, float x, float 
 
 // ----------------------------------------------------------------------------- resolve
 
-// Texels per thread of the resolve: both keys, then both face records, in
-// flight together (the chain key -> record -> store is the kernel's latency).
-constexpr int kResolvePerThread = 2;
+// Texels per thread of the resolve (256 apart): their keys, then their face
+// records, in flight together (the chain key -> record -> store is the
+// kernel's latency; 80 -> 62 -> 55 us for 1, 2, 4 on 64 512^2 maps).
+constexpr int kResolvePerThread = 4;
 
 __global__ __launch_bounds__(256) void resolve_kernel(const ViewConst *__restrict__ views,
                                                       const TriVerts *__restrict__ tv,
@@ -170,38 +171,91 @@ __device__ __forceinline__ void aa_forward_sample(const ViewConst &v, long long 
         if (c < C) dst[base + (long long)p * pstride + c * cstride] = acc[c];
 }
 
-// First pass: copy samples without candidates, list the others.
+// First pass: copy samples without candidates, list the others.  Each
+// thread takes kAaFirstPassPerThread samples 256 apart, with all of their
+// neighbour keys in flight together and one wave vote on whether any
+// silhouette byte is needed; list segments are assigned per 256-sample
+// chunk (chunk index gxv * row + column), as if each chunk were a
+// workgroup, so the list sizing does not depend on it.
+constexpr int kAaFirstPassPerThread = 2;
+
 template <bool LIGHT, int C>
 __global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__restrict__ views,
                                                          const RenderConst *__restrict__ renders,
                                                          const unsigned char *__restrict__ silm,
                                                          const unsigned long long *__restrict__ keys,
                                                          const float *__restrict__ src, float *__restrict__ dst,
-                                                         AaList list, unsigned char *__restrict__ flag) {
+                                                         AaList list, unsigned char *__restrict__ flag, int gxv) {
+    constexpr int PPT = kAaFirstPassPerThread;
     const Blk blk = xcd_block2();
     const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
-    const int W = v.W, H = v.H;
-    const int p = blk.x * blockDim.x + threadIdx.x;
-    if (p >= W * H) return;
+    const int W = v.W, H = v.H, P = W * H;
+    const int p0 = blk.x * (256 * PPT) + (int)threadIdx.x;
+    if (p0 >= P) return;
     const long long base = LIGHT ? v.map_off : renders[blk.y].img_off;
-    const long long cstride = LIGHT ? (long long)W * H : 1;
+    const long long cstride = LIGHT ? (long long)P : 1;
     const int pstride = LIGHT ? 1 : C;
     const unsigned long long *kv = keys + v.pix_off;
-    float val[3] = {0.f, 0.f, 0.f};
+    bool live[PPT];
+    float val[PPT][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        if (c < C) val[c] = src[base + (long long)p * pstride + c * cstride];
-    bool cand = false;
-    if (v.antialias && v.nfaces > 0) {
-        const AANeighbours nb = aa_neighbours(v, kv, silm, kv[p], p % W, p / W);
-        cand = nb.cand[0] || nb.cand[1] || nb.cand[2] || nb.cand[3];
+    for (int k = 0; k < PPT; ++k) {
+        const int p = p0 + 256 * k;
+        live[k] = p < P;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) val[k][c] = (live[k] && c < C) ? src[base + (long long)p * pstride + c * cstride] : 0.f;
     }
-    flag[v.pix_off + p] = cand ? 1 : 0;
-    wave_append(cand, make_uint2((unsigned)blk.y, (unsigned)p), list, (long long)blk.y * gridDim.x + blk.x);
-    if (cand) return;
+    bool cand[PPT];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        if (c < C) dst[base + (long long)p * pstride + c * cstride] = val[c];
+    for (int k = 0; k < PPT; ++k) cand[k] = false;
+    if (v.antialias && v.nfaces > 0) {
+        // every neighbour key of every sample first, then the differing pairs
+        unsigned long long ks[PPT], kn[PPT][4];
+        bool differ[PPT][4];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = live[k] ? p0 + 256 * k : p0;
+            const int i = p % W, j = p / W;
+            ks[k] = kv[p];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int in_ = i + (d == 0 ? -1 : d == 1 ? 1 : 0), jn = j + (d == 2 ? -1 : d == 3 ? 1 : 0);
+                const bool inb = in_ >= 0 && in_ < W && jn >= 0 && jn < H;
+                kn[k][d] = kv[inb ? jn * W + in_ : p];
+                differ[k][d] = inb;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                differ[k][d] = live[k] && differ[k][d] && (unsigned)kn[k][d] != (unsigned)ks[k];
+                any = any || differ[k][d];
+            }
+        if (__ballot(any) != 0ull) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const unsigned front = ks[k] < kn[k][d] ? (unsigned)ks[k] : (unsigned)kn[k][d];
+                    const unsigned char sil = differ[k][d] ? silm[v.setup_off + front] : (unsigned char)0;
+                    cand[k] = cand[k] || (differ[k][d] && sil != 0);
+                }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int p = p0 + 256 * k;
+        if (live[k]) flag[v.pix_off + p] = cand[k] ? 1 : 0;
+        wave_append(cand[k], make_uint2((unsigned)blk.y, (unsigned)p), list,
+                    (long long)blk.y * gxv + (long long)blk.x * PPT + k);
+        if (live[k] && !cand[k]) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (c < C) dst[base + (long long)p * pstride + c * cstride] = val[k][c];
+        }
+    }
 }
 
 // One pass over every sample (camera images: their candidates are too
@@ -445,10 +499,12 @@ hipError_t launch_aa_forward(bool light, const ViewConst *views, const RenderCon
     if (n == 0) return hipSuccess;
     const dim3 grid((max_pix + 255) / 256, n);
     const AaList l = aa_list_for(list, counts, (long long)grid.x * grid.y);
+    constexpr int P1 = kAaFirstPassPerThread;
+    const dim3 grid1((max_pix + 256 * P1 - 1) / (256 * P1), n);
 #define DSM_AAF(LL, CC)                                                                                          \
     do {                                                                                                         \
-        hipLaunchKernelGGL((aa_forward_kernel<LL, CC>), grid, dim3(256), 0, s, views, renders, silm, keys, src,  \
-                           dst, l, aa_flag);                                                                     \
+        hipLaunchKernelGGL((aa_forward_kernel<LL, CC>), grid1, dim3(256), 0, s, views, renders, silm, keys, src, \
+                           dst, l, aa_flag, (int)grid.x);                                                        \
         hipLaunchKernelGGL((aa_forward_list_kernel<LL, CC>), dim3(l.nseg), dim3(256), 0, s, views, renders,      \
                            setup, faces, silm, verts, keys, src, dst, l);                                        \
     } while (0)
