@@ -50,10 +50,10 @@ HBM_PEAK_GBS = 8000.0
 # had when the counters were taken (and at tile side 8, where they were).
 PMC_COPY = dict(fetch_kib=65547.6, write_kib=131072.0, moved_kib=131072.0)
 PMC = {
-    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=65766.5, write_kib=131072.0, rd_bytes=134614976, wr_bytes=134217728, waves=32768, valu_per_wave=716.2, valu_busy=0.598, occupancy=19.7, sources=('blur.hip', 'dsm_internal.h'), sha1='83625a0639e923ef'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65621.9, write_kib=131072.0, rd_bytes=134309338, wr_bytes=134217728, waves=32768, valu_per_wave=943.1, valu_busy=0.798, occupancy=20.3, sources=('blur.hip', 'dsm_internal.h'), sha1='83625a0639e923ef'),
-    'lookup': dict(kernel='lookup_kernel<2>', fetch_kib=200702.0, write_kib=65536.0, rd_bytes=410716966, wr_bytes=67108864, waves=131072, valu_per_wave=532.6, valu_busy=1.071, occupancy=26.0, sources=('shade.hip', 'dsm_internal.h'), sha1='f5fa9ab841af2a33'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=117287.9, write_kib=120141.1, rd_bytes=239957990, wr_bytes=123024230, waves=262144, valu_per_wave=898.0, valu_busy=0.799, occupancy=14.8, sources=('grad.hip', 'dsm_internal.h'), sha1='2341965364481d95'),
+    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=65787.7, write_kib=131072.0, rd_bytes=134669491, wr_bytes=134217728, waves=32768, valu_per_wave=716.2, valu_busy=0.606, occupancy=19.7, sources=('blur.hip', 'dsm_internal.h'), sha1='c1ce77dba9caff8f'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65621.9, write_kib=131072.0, rd_bytes=134308544, wr_bytes=134217728, waves=32768, valu_per_wave=943.1, valu_busy=0.796, occupancy=20.5, sources=('blur.hip', 'dsm_internal.h'), sha1='c1ce77dba9caff8f'),
+    'lookup': dict(kernel='lookup_kernel<2>', fetch_kib=200691.0, write_kib=65536.0, rd_bytes=410705395, wr_bytes=67108864, waves=131072, valu_per_wave=466.0, valu_busy=0.955, occupancy=26.1, sources=('shade.hip', 'dsm_internal.h'), sha1='c665379584c2dbea'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=117291.9, write_kib=120144.7, rd_bytes=239961677, wr_bytes=123027994, waves=262144, valu_per_wave=854.4, valu_busy=0.765, occupancy=14.9, sources=('grad.hip', 'dsm_internal.h'), sha1='b12c94bbe262c312'),
 }
 
 # Issue peak of the vector ALUs: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per
