@@ -59,10 +59,12 @@ __device__ __forceinline__ void wave_add(const float (&val)[N], float *dst) {
     }
 }
 
-// Reciprocal (about one ulp) for quotients that decide no coverage, cell or
-// index (gradient terms, and the shading values the adjoints recompute exactly
-// as the forward kernels form them): the correctly rounded division the
-// raster setup needs costs about ten instructions, this one.
+// Reciprocal (about one ulp) for gradient terms and for the shading values
+// the adjoints recompute exactly as the forward kernels form them (the map
+// position, which picks the bilinear cell, among them: both passes take that
+// decision from the same float32 value).  The correctly rounded division,
+// which the raster setup keeps for its integer results, costs about ten
+// instructions, this one.
 __device__ __forceinline__ float grcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // NDC of pixel centre i of n, as the forward resolve and lookup form it.

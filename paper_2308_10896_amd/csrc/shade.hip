@@ -43,9 +43,12 @@ __device__ __forceinline__ Bary persp_bary_rcp(float4 c0, float4 c1, float4 c2, 
     return Bary{k0 * rs, k1 * rs, k2 * rs};
 }
 
-// The shading and resolve arithmetic below decides no coverage or index, so
-// its quotients go through the hardware reciprocal (about 1 ulp) instead of
-// the correctly rounded division the raster setup needs.
+// The resolve and the lookup form their quotients through the hardware
+// reciprocal (about 1 ulp), where the raster setup, whose coverage and depth
+// keys are integer results, keeps the correctly rounded division.  The
+// lookup's adjoint forms every value with the same expressions (the map
+// position, which picks the bilinear cell and the inside test, among them),
+// so the two passes take the same decisions.
 __device__ __forceinline__ float ndc_centre(int i, int n) {
     return (float)(2 * i + 1) * __builtin_amdgcn_rcpf((float)n) - 1.0f;
 }
