@@ -169,6 +169,22 @@ __device__ __forceinline__ AANeighbours aa_neighbours(const ViewConst &v, const 
     return n;
 }
 
+// Sample of thread t of workgroup b (256 threads) in a W x H view.  When
+// the view is a whole number of 32 x 8 regions, each workgroup takes one
+// region and each wave one 8 x 8 tile of it, so that a silhouette touches
+// fewer waves than with row segments of 64 samples (a wave with one
+// candidate pair waits for the pair tests' loads on all of its lanes);
+// otherwise samples run in row order.  Either way the workgroups cover the
+// view's W * H samples exactly once.
+__device__ __forceinline__ int aa_sample_index(int b, int t, int W, int H) {
+    if ((W & 31) == 0 && (H & 7) == 0) {
+        const int rx = b % (W >> 5), ry = b / (W >> 5);
+        const int w = t >> 6, l = t & 63;
+        return (ry * 8 + (l >> 3)) * W + rx * 32 + w * 8 + (l & 7);
+    }
+    return b * 256 + t;
+}
+
 // Samples listed for the second pass of the smoothing kernels.  The list is
 // cut into segments, each with its own counter, so that the appends of
 // different workgroups do not contend for one address: workgroup b of the

@@ -119,8 +119,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
     const RenderConst &R = renders[blk.y];
     const ViewConst &v = views[R.camera_view];
     const int W = v.W, H = v.H;
-    const int p = blk.x * blockDim.x + threadIdx.x;
-    if (p >= W * H) return;
+    const int p = aa_sample_index(blk.x, (int)threadIdx.x, W, H);
+    if (blk.x * 256 >= W * H || p >= W * H) return;
     const float *c0 = img0 + R.img_off;
     const float *g = gimg + R.img_off;
     float acc[3] = {0.f, 0.f, 0.f};

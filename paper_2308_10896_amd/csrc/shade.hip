@@ -175,9 +175,10 @@ __device__ __forceinline__ void aa_forward_sample(const ViewConst &v, long long 
 }
 
 // First pass: copy samples without candidates, list the others.  Each
-// thread takes kAaFirstPassPerThread samples 256 apart, with all of their
-// neighbour keys in flight together and one wave vote on whether any
-// silhouette byte is needed; list segments are assigned per 256-sample
+// thread takes one sample of each of kAaFirstPassPerThread consecutive
+// 256-sample chunks (32 x 8 regions where the view allows, aa_sample_index),
+// with all of their neighbour keys in flight together and one wave vote on
+// whether any silhouette byte is needed; list segments are assigned per
 // chunk (chunk index gxv * row + column), as if each chunk were a
 // workgroup, so the list sizing does not depend on it.
 constexpr int kAaFirstPassPerThread = 2;
@@ -193,18 +194,24 @@ __global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__rest
     const Blk blk = xcd_block2();
     const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
     const int W = v.W, H = v.H, P = W * H;
-    const int p0 = blk.x * (256 * PPT) + (int)threadIdx.x;
-    if (p0 >= P) return;
+    // sample k of this thread: thread t of the 256-sample chunk blk.x * PPT + k
+    int ps[PPT];
+    bool live[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int b = blk.x * PPT + k;
+        ps[k] = aa_sample_index(b, (int)threadIdx.x, W, H);
+        live[k] = b * 256 < P && ps[k] < P;
+    }
+    if (!live[0]) return;
     const long long base = LIGHT ? v.map_off : renders[blk.y].img_off;
     const long long cstride = LIGHT ? (long long)P : 1;
     const int pstride = LIGHT ? 1 : C;
     const unsigned long long *kv = keys + v.pix_off;
-    bool live[PPT];
     float val[PPT][3];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int p = p0 + 256 * k;
-        live[k] = p < P;
+        const int p = ps[k];
 #pragma unroll
         for (int c = 0; c < 3; ++c) val[k][c] = (live[k] && c < C) ? src[base + (long long)p * pstride + c * cstride] : 0.f;
     }
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__rest
         bool any = false;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int p = live[k] ? p0 + 256 * k : p0;
+            const int p = live[k] ? ps[k] : ps[0];
             const int i = p % W, j = p / W;
             ks[k] = kv[p];
 #pragma unroll
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__rest
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int p = p0 + 256 * k;
+        const int p = ps[k];
         if (live[k]) flag[v.pix_off + p] = cand[k] ? 1 : 0;
         wave_append(cand[k], make_uint2((unsigned)blk.y, (unsigned)p), list,
                     (long long)blk.y * gxv + (long long)blk.x * PPT + k);
@@ -273,8 +280,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
     const Blk blk = xcd_block2();
     const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
     const int W = v.W, H = v.H;
-    const int p = blk.x * blockDim.x + threadIdx.x;
-    if (p >= W * H) return;
+    const int p = aa_sample_index(blk.x, (int)threadIdx.x, W, H);
+    if (blk.x * 256 >= W * H || p >= W * H) return;
     const long long base = LIGHT ? v.map_off : renders[blk.y].img_off;
     const long long cstride = LIGHT ? (long long)W * H : 1;
     const int pstride = LIGHT ? 1 : C;
