@@ -175,12 +175,12 @@ __device__ __forceinline__ void aa_forward_sample(const ViewConst &v, long long 
 }
 
 // First pass: copy samples without candidates, list the others.  Each
-// thread takes one sample of each of kAaFirstPassPerThread consecutive
-// 256-sample chunks (32 x 8 regions where the view allows, aa_sample_index),
-// with all of their neighbour keys in flight together and one wave vote on
-// whether any silhouette byte is needed; list segments are assigned per
+// thread takes kAaFirstPassPerThread samples 256 apart, with all of their
+// neighbour keys in flight together and one wave vote on whether any
+// silhouette byte is needed; list segments are assigned per 256-sample
 // chunk (chunk index gxv * row + column), as if each chunk were a
-// workgroup, so the list sizing does not depend on it.
+// workgroup, so the list sizing does not depend on it.  Samples run in row
+// order: this pass streams, and has no candidate tests to concentrate.
 constexpr int kAaFirstPassPerThread = 2;
 
 template <bool LIGHT, int C>
@@ -194,16 +194,15 @@ __global__ __launch_bounds__(256) void aa_forward_kernel(const ViewConst *__rest
     const Blk blk = xcd_block2();
     const ViewConst &v = LIGHT ? views[blk.y] : views[renders[blk.y].camera_view];
     const int W = v.W, H = v.H, P = W * H;
-    // sample k of this thread: thread t of the 256-sample chunk blk.x * PPT + k
+    const int p0 = blk.x * (256 * PPT) + (int)threadIdx.x;
+    if (p0 >= P) return;
     int ps[PPT];
     bool live[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int b = blk.x * PPT + k;
-        ps[k] = aa_sample_index(b, (int)threadIdx.x, W, H);
-        live[k] = b * 256 < P && ps[k] < P;
+        ps[k] = p0 + 256 * k;
+        live[k] = ps[k] < P;
     }
-    if (!live[0]) return;
     const long long base = LIGHT ? v.map_off : renders[blk.y].img_off;
     const long long cstride = LIGHT ? (long long)P : 1;
     const int pstride = LIGHT ? 1 : C;
