@@ -25,10 +25,32 @@ namespace dsm {
 
 // ----------------------------------------------------------------------------- light frames
 
+// The Jacobian of (M[16], pos[3], dir[3]) with respect to the three
+// parameter components (forward-mode dual numbers), [22][3] per light: the
+// reverse pass pulls every light-frame gradient back to the parameter as
+// soon as it is formed.
+__device__ void light_jacobian(const CamStatic &cam, const float *param, float *J) {
+    Dual3 pd[3];
+    for (int i = 0; i < 3; ++i) {
+        pd[i].v = param[i];
+        for (int j = 0; j < 3; ++j) pd[i].d[j] = (i == j) ? 1.0 : 0.0;
+    }
+    Dual3 Md[16], posd[3], dird[3];
+    light_frame<Dual3>(cam, pd, Md, posd, dird);
+    for (int j = 0; j < 3; ++j) {
+        for (int i = 0; i < 16; ++i) J[3 * i + j] = (float)Md[i].d[j];
+        for (int i = 0; i < 3; ++i) {
+            J[3 * (16 + i) + j] = (float)posd[i].d[j];
+            J[3 * (19 + i) + j] = (float)dird[i].d[j];
+        }
+    }
+}
+
 // One thread per light: the light camera from its float32 parameter, in
-// float64, rounded to float32 for the rest of the pipeline.
+// float64, rounded to float32 for the rest of the pipeline; with jac, also
+// the frame's Jacobian (one launch for both).
 __global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L,
-                                    float *zc_out) {
+                                    float *zc_out, float *jac) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L) return;
     const double p[3] = {params[3 * l], params[3 * l + 1], params[3 * l + 2]};
@@ -42,30 +64,7 @@ __global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, con
     }
     v.zc = (float)light_reference_depth(cams[l], p);
     if (zc_out) zc_out[l] = v.zc;
-}
-
-// The Jacobian of (M[16], pos[3], dir[3]) with respect to the three
-// parameter components (forward-mode dual numbers), [22][3] per light: the
-// reverse pass pulls every light-frame gradient back to the parameter as
-// soon as it is formed.
-__global__ void light_jacobian_kernel(const CamStatic *cams, const float *params, int L, float *jac) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= L) return;
-    Dual3 pd[3];
-    for (int i = 0; i < 3; ++i) {
-        pd[i].v = params[3 * l + i];
-        for (int j = 0; j < 3; ++j) pd[i].d[j] = (i == j) ? 1.0 : 0.0;
-    }
-    Dual3 Md[16], posd[3], dird[3];
-    light_frame<Dual3>(cams[l], pd, Md, posd, dird);
-    float *J = jac + (size_t)kJac * l;
-    for (int j = 0; j < 3; ++j) {
-        for (int i = 0; i < 16; ++i) J[3 * i + j] = (float)Md[i].d[j];
-        for (int i = 0; i < 3; ++i) {
-            J[3 * (16 + i) + j] = (float)posd[i].d[j];
-            J[3 * (19 + i) + j] = (float)dird[i].d[j];
-        }
-    }
+    if (jac) light_jacobian(cams[l], params + 3 * l, jac + (size_t)kJac * l);
 }
 
 // ----------------------------------------------------------------------------- transform
@@ -371,6 +370,7 @@ __global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriS
                                  unsigned *__restrict__ bin_pair, unsigned *__restrict__ big_list,
                                  DevCounters *counters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!FILL && i == 0) counters->pairs = pair_off[ntri];   // total pairs, for the plan's statistics
     unsigned a = 0, b = 0;
     if (i < ntri) {
         a = pair_off[i];
@@ -425,9 +425,6 @@ __global__ void bin_big_kernel(const ViewConst *__restrict__ views, const TriSet
     }
 }
 
-__global__ void pairs_total_kernel(const unsigned *pair_off, int ntri, DevCounters *counters) {
-    counters->pairs = pair_off[ntri];
-}
 
 __global__ void overflow_list_kernel(const unsigned *__restrict__ pair_off, int ntri, unsigned capacity,
                                      unsigned *__restrict__ list, DevCounters *counters) {
@@ -575,11 +572,13 @@ __global__ __launch_bounds__(kRasterThreads) void raster_kernel(
 }
 
 // Triangles that did not fit the bins: one workgroup per listed triangle at
-// a time, atomic minimum over its bounding box.
+// a time, atomic minimum over its bounding box.  The first thread also adds
+// the list's length to the overflow count.
 __global__ void overflow_raster_kernel(const ViewConst *__restrict__ views, const TriSetup *__restrict__ setup,
-                                       const unsigned *__restrict__ list, const DevCounters *counters,
+                                       const unsigned *__restrict__ list, DevCounters *counters,
                                        unsigned long long *__restrict__ keys) {
     const unsigned n = counters->overflow_list_len;
+    if (blockIdx.x == 0 && threadIdx.x == 0) counters->overflow += n;
     for (unsigned o = blockIdx.x; o < n; o += gridDim.x) {
         const unsigned si = list[o];
         const TriSetup &s = setup[si];
@@ -596,17 +595,13 @@ __global__ void overflow_raster_kernel(const ViewConst *__restrict__ views, cons
     }
 }
 
-__global__ void overflow_count_kernel(DevCounters *counters) {
-    counters->overflow += counters->overflow_list_len;
-}
-
 // ----------------------------------------------------------------------------- host launchers
 
 hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
                                float *zc_out, hipStream_t s) {
     if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L, zc_out);
-    if (jac) hipLaunchKernelGGL(light_jacobian_kernel, dim3((L + 63) / 64), dim3(64), 0, s, cams, params, L, jac);
+    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L, zc_out,
+                       jac);
     return hipGetLastError();
 }
 
@@ -637,7 +632,6 @@ hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const u
                           unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
                           unsigned *pair_slot, unsigned *scan_scratch, int ntiles, unsigned *bins,
                           unsigned *bin_pair, unsigned *overflow_list, DevCounters *counters, hipStream_t s) {
-    hipLaunchKernelGGL(pairs_total_kernel, dim3(1), dim3(1), 0, s, pair_off, ntri, counters);
     // the list of large triangles lives in overflow_list until the overflow list is built below
     const dim3 tgrid((ntri + 255) / 256);
     const dim3 bgrid(1024);
@@ -680,9 +674,8 @@ hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntile
             hipLaunchKernelGGL(raster_kernel<32>, dim3(ntiles), dim3(256), 0, s, views, tile_view, setup, tile_start,
                                bins, keys);
     }
-    hipLaunchKernelGGL(overflow_raster_kernel, dim3(512), dim3(256), 0, s, views, setup, overflow_list, counters_ro,
+    hipLaunchKernelGGL(overflow_raster_kernel, dim3(512), dim3(256), 0, s, views, setup, overflow_list, counters,
                        keys);
-    hipLaunchKernelGGL(overflow_count_kernel, dim3(1), dim3(1), 0, s, counters);
     return hipGetLastError();
 }
 
