@@ -258,31 +258,24 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(const unsigne
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-// single block; nb <= kScanBlock; writes the grand total to block_sums[nb]
-__global__ __launch_bounds__(kScanThreads) void scan_sums_kernel(unsigned *block_sums, int nb) {
-    const int base = threadIdx.x * kScanPer;
-    unsigned vals[kScanPer];
-    unsigned sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        vals[k] = (base + k < nb) ? block_sums[base + k] : 0u;
-        sum += vals[k];
+// One workgroup per scan block: its offset is the sum of the block sums
+// before it (nb <= kScanBlock, so each thread adds at most kScanPer of
+// them), added to the block's kScanBlock outputs.  The last block also
+// writes the grand total to out[n]; with n = 0 one workgroup writes 0.
+__global__ __launch_bounds__(kScanThreads) void scan_add_kernel(unsigned *out, const unsigned *block_sums, int n,
+                                                                int nb) {
+    const int b = blockIdx.x;
+    unsigned part = 0;
+    for (int k = threadIdx.x; k < b; k += kScanThreads) part += block_sums[k];
+    unsigned off;
+    block_exclusive_scan(part, &off);
+    const long long base = (long long)b * kScanBlock;
+    for (int k = threadIdx.x; k < kScanBlock; k += kScanThreads)
+        if (base + k < n) out[base + k] += off;
+    if (threadIdx.x == 0) {
+        if (nb == 0) out[0] = 0u;
+        else if (b == nb - 1) out[n] = off + block_sums[b];
     }
-    unsigned total;
-    unsigned off = block_exclusive_scan(sum, &total);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        if (base + k < nb) block_sums[base + k] = off;
-        off += vals[k];
-    }
-    if (threadIdx.x == 0) block_sums[nb] = total;
-}
-
-__global__ void scan_add_kernel(unsigned *out, const unsigned *block_sums, int n, int nb) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] += block_sums[i / kScanBlock];
-    if (i == 0) out[n] = block_sums[nb];
 }
 
 // Exclusive scan of n values in place-capable form: out[0..n] (out[n] = total).
@@ -293,8 +286,7 @@ hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int
     const int nb = (n + kScanBlock - 1) / kScanBlock;
     if (nb > kScanBlock) return hipErrorInvalidValue;
     if (nb > 0) hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, out, scratch, n);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, scratch, nb);
-    hipLaunchKernelGGL(scan_add_kernel, dim3((n + 256) / 256), dim3(256), 0, s, out, scratch, n, nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(nb > 0 ? nb : 1), dim3(kScanThreads), 0, s, out, scratch, n, nb);
     return hipGetLastError();
 }
 
