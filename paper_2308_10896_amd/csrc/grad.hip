@@ -1136,6 +1136,27 @@ __global__ __launch_bounds__(256) void big_pair_reduce_kernel(const unsigned *__
     }
 }
 
+// Albedo gradient per face: sum over the camera views of its scene.  Run by
+// the workgroups of the vertex gather's launch past its vertex blocks
+// (column bx of scene b).
+__device__ __forceinline__ void albedo_gather_block(const ViewConst *__restrict__ views, int L, int b, int bx,
+                                                    const int *__restrict__ scene_face_off,
+                                                    const int *__restrict__ scene_views_off,
+                                                    const int *__restrict__ scene_views,
+                                                    const float *__restrict__ gtri, float *__restrict__ galbedo,
+                                                    int C) {
+    const int fl = bx * blockDim.x + threadIdx.x;
+    if (fl >= scene_face_off[b + 1] - scene_face_off[b]) return;
+    float acc[3] = {0, 0, 0};
+    for (int s = scene_views_off[b]; s < scene_views_off[b + 1]; ++s) {
+        const int vi = scene_views[s];
+        if (vi < L) continue;
+        const float *row = gtri + (size_t)(views[vi].setup_off + fl) * kGtriStride;
+        for (int c = 0; c < C; ++c) acc[c] += row[gtri_slot(18 + c)];
+    }
+    for (int c = 0; c < C; ++c) galbedo[(size_t)(scene_face_off[b] + fl) * C + c] = acc[c];
+}
+
 // Per vertex: sum its triangle corners' terms over every view of its scene,
 // add the silhouette clip terms, map clip terms through M^T; per light view
 // the workgroup's share of dL/dM is written for glight_reduce.
@@ -1144,8 +1165,14 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
     const int *__restrict__ scene_views_off, const int *__restrict__ scene_views, const int *__restrict__ vc_off,
     const int *__restrict__ vc_list, const float *__restrict__ verts, const float *__restrict__ gtri,
     const float *__restrict__ zero_rec, const float4 *__restrict__ gclip, float *__restrict__ gverts,
-    float *__restrict__ part_gm, const float *__restrict__ jac) {
+    float *__restrict__ part_gm, const float *__restrict__ jac, int vx, const int *__restrict__ scene_face_off,
+    float *__restrict__ galbedo, int C) {
     const int b = blockIdx.y;
+    if ((int)blockIdx.x >= vx) {                               // the albedo gather's workgroups
+        albedo_gather_block(views, L, b, (int)blockIdx.x - vx, scene_face_off, scene_views_off, scene_views, gtri,
+                            galbedo, C);
+        return;
+    }
     const int nv = scene_vert_off[b + 1] - scene_vert_off[b];
     if ((int)(blockIdx.x * blockDim.x) >= nv) return;        // whole workgroup
     const int vl = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1238,23 +1265,6 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(
     }
     if (in)
         for (int k = 0; k < 3; ++k) gverts[3 * (size_t)gv_idx + k] = gv[k];
-}
-
-// Albedo gradient per face: sum over the camera views of its scene.
-__global__ void albedo_gather_kernel(const ViewConst *__restrict__ views, int L, const int *__restrict__ scene_face_off,
-                                     const int *__restrict__ scene_views_off, const int *__restrict__ scene_views,
-                                     const float *__restrict__ gtri, float *__restrict__ galbedo, int C) {
-    const int b = blockIdx.y;
-    const int fl = blockIdx.x * blockDim.x + threadIdx.x;
-    if (fl >= scene_face_off[b + 1] - scene_face_off[b]) return;
-    float acc[3] = {0, 0, 0};
-    for (int s = scene_views_off[b]; s < scene_views_off[b + 1]; ++s) {
-        const int vi = scene_views[s];
-        if (vi < L) continue;
-        const float *row = gtri + (size_t)(views[vi].setup_off + fl) * kGtriStride;
-        for (int c = 0; c < C; ++c) acc[c] += row[gtri_slot(18 + c)];
-    }
-    for (int c = 0; c < C; ++c) galbedo[(size_t)(scene_face_off[b] + fl) * C + c] = acc[c];
 }
 
 // glight[l] = sum of every partial written for light l (vertex blocks, light
@@ -1494,13 +1504,12 @@ hipError_t launch_vertex_gradients(const ViewConst *views, int L, int B, int max
                            big_list,
                            (const unsigned *)big_count);
     }
-    if (max_verts > 0)
-        hipLaunchKernelGGL(vertex_gather_kernel, dim3((max_verts + 255) / 256, B), dim3(256), 0, s, views, L,
-                           scene_vert_off, scene_views_off, scene_views, vc_off, vc_list, verts, gtri, zero_rec, gclip,
-                           gverts, part_gm, jac);
-    if (galbedo && max_faces > 0)
-        hipLaunchKernelGGL(albedo_gather_kernel, dim3((max_faces + 255) / 256, B), dim3(256), 0, s, views, L,
-                           scene_face_off, scene_views_off, scene_views, gtri, galbedo, C);
+    // one launch: the vertex gather's workgroups, then the albedo gather's
+    const int vx = (max_verts + 255) / 256, fx = (galbedo && max_faces > 0) ? (max_faces + 255) / 256 : 0;
+    if (B > 0 && vx + fx > 0)
+        hipLaunchKernelGGL(vertex_gather_kernel, dim3(vx + fx, B), dim3(256), 0, s, views, L, scene_vert_off,
+                           scene_views_off, scene_views, vc_off, vc_list, verts, gtri, zero_rec, gclip, gverts,
+                           part_gm, jac, vx, scene_face_off, galbedo, C);
     return hipGetLastError();
 }
 
