@@ -349,7 +349,8 @@ __device__ __forceinline__ unsigned wave_aggregated_slot(bool has, int g, unsign
 }
 
 // Triangles with at most kBigBin pairs: one thread each.  Larger ones are
-// listed (count pass) and handled a workgroup each by bin_big_kernel.
+// listed (count pass) and handled a workgroup each, by bin_big_kernel in the
+// count pass and by the fill pass's workgroups past nsmall.
 // Triangles whose pair range does not fit the bin capacity go to the
 // overflow path instead (decided per triangle, so never split).
 constexpr unsigned kBigBin = 32;
@@ -360,7 +361,18 @@ __global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriS
                                  unsigned *__restrict__ tile_count, unsigned *__restrict__ pair_slot,
                                  const unsigned *__restrict__ tile_start, unsigned *__restrict__ bins,
                                  unsigned *__restrict__ bin_pair, unsigned *__restrict__ big_list,
-                                 DevCounters *counters) {
+                                 DevCounters *counters, int nsmall) {
+    if (FILL && (int)blockIdx.x >= nsmall) {
+        // workgroups past the triangles' own: the listed large triangles, a
+        // workgroup each (their list is complete after the count pass)
+        const unsigned n = counters->big_bin_len;
+        for (unsigned o = blockIdx.x - nsmall; o < n; o += gridDim.x - nsmall) {
+            const int t = (int)big_list[o];
+            bin_pairs<true>(views, setup[t], t, pair_off[t], pair_off[t + 1], tile, threadIdx.x, blockDim.x, tile_count,
+                            pair_slot, tile_start, bins, bin_pair);
+        }
+        return;
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (!FILL && i == 0) counters->pairs = pair_off[ntri];   // total pairs, for the plan's statistics
     unsigned a = 0, b = 0;
@@ -630,7 +642,7 @@ hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const u
     if (ntri > 0) {
         hipLaunchKernelGGL(bin_small_kernel<false>, tgrid, dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
                            tile_count, pair_slot, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
-                           overflow_list, counters);
+                           overflow_list, counters, (int)tgrid.x);
         hipLaunchKernelGGL(bin_big_kernel<false>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile, tile_count,
                            pair_slot, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
                            (const unsigned *)overflow_list, (const DevCounters *)counters);
@@ -638,12 +650,10 @@ hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const u
     hipError_t e = launch_scan(tile_count, tile_start, scan_scratch, ntiles, s);
     if (e != hipSuccess) return e;
     if (ntri > 0) {
-        hipLaunchKernelGGL(bin_small_kernel<true>, tgrid, dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
-                           (unsigned *)nullptr, pair_slot, (const unsigned *)tile_start, bins, bin_pair, overflow_list,
-                           counters);
-        hipLaunchKernelGGL(bin_big_kernel<true>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile,
-                           (unsigned *)nullptr, pair_slot, (const unsigned *)tile_start, bins, bin_pair,
-                           (const unsigned *)overflow_list, (const DevCounters *)counters);
+        // the fill pass and the large triangles' fill in one launch (bgrid.x extra workgroups)
+        hipLaunchKernelGGL(bin_small_kernel<true>, dim3(tgrid.x + bgrid.x), dim3(256), 0, s, views, setup, pair_off,
+                           ntri, capacity, tile, (unsigned *)nullptr, pair_slot, (const unsigned *)tile_start, bins,
+                           bin_pair, overflow_list, counters, (int)tgrid.x);
     }
     if (ntri > 0)
         hipLaunchKernelGGL(overflow_list_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
