@@ -530,6 +530,7 @@ extern "C" dsm_status dsm_plan_create(const dsm_batch_desc *d, int32_t tile_size
     p->sc_scan = o; o = align_up(o + 4 * (size_t)std::max(scan_scratch_words((int)tri), scan_scratch_words((int)tiles)) + 64);
     p->sc_facing = o; o = align_up(o + (size_t)tri + 1);
     p->sc_pair_slot = o; o = align_up(o + 4 * (size_t)p->capacity);    // each pair's slot in its tile's bin
+    p->sc_big_bin = o; o = align_up(o + 4 * ((size_t)tri + 1));       // triangles binned a workgroup each
     // light-map samples whose smoothing has candidate pairs: the segmented list of the light smoothing
     // grid (launch_aa_forward cuts it the same way)
     {
@@ -732,7 +733,8 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     DSM_MARK(DSM_STAGE_BIN);
     DSM_TRY(launch_scan(pair_cnt, pair_off, scan, p->ntri, s));
     DSM_TRY(launch_binning(p->views_d, setup, pair_off, p->ntri, p->capacity, p->tile, tile_cnt, tile_start,
-                           pair_slot, scan, p->ntiles, bins, bin_pair, overflow, cnt, s));
+                           pair_slot, scan, p->ntiles, bins, bin_pair, overflow, at<unsigned>(scratch, p->sc_big_bin), cnt,
+                           s));
     DSM_MARK(DSM_STAGE_RASTER);
     DSM_TRY(launch_raster(p->views_d, p->tile_view_d, p->ntiles, p->tile, setup, tile_start, bins, overflow, cnt, cnt,
                           keys, s));

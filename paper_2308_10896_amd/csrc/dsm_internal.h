@@ -296,7 +296,8 @@ hipError_t launch_scan(const unsigned *in, unsigned *out, unsigned *scratch, int
 hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,
                           unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
                           unsigned *pair_slot, unsigned *scan_scratch, int ntiles, unsigned *bins,
-                          unsigned *bin_pair, unsigned *overflow_list, DevCounters *counters, hipStream_t s);
+                          unsigned *bin_pair, unsigned *overflow_list, unsigned *big_list, DevCounters *counters,
+                          hipStream_t s);
 hipError_t launch_raster(const ViewConst *views, const int *tile_view, int ntiles, int tile, const TriSetup *setup,
                          const unsigned *tile_start, const unsigned *bins, const unsigned *overflow_list,
                          const DevCounters *counters_ro, DevCounters *counters, unsigned long long *keys,

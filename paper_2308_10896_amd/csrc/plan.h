@@ -68,7 +68,7 @@ struct dsm_plan {
            saved_bytes = 0;
     // layout of the caller's scratch buffer (byte offsets): temporaries of
     // one call, nothing carried from a forward to its backward
-    size_t sc_pair_cnt = 0, sc_scan = 0, sc_tile_cnt = 0, sc_facing = 0,
+    size_t sc_pair_cnt = 0, sc_scan = 0, sc_tile_cnt = 0, sc_facing = 0, sc_big_bin = 0,
            sc_pair_slot = 0, sc_aa_list = 0, sc_aa_count = 0, sc_pair_flag = 0, sc_F1 = 0, sc_fwd_end = 0, sc_gimg0 = 0, sc_gM = 0, sc_gF1 = 0,
            sc_gclip = 0, sc_glight = 0, sc_zero_fwd_end = 0, sc_bigcount = 0, sc_zero_rec = 0, sc_zero_bwd_end = 0,
            sc_pair_sums = 0, sc_gtri = 0, sc_biglist = 0, sc_part_light = 0, sc_part_gm = 0, sc_part_render = 0, sc_jac = 0,

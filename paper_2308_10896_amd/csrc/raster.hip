@@ -361,7 +361,7 @@ __global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriS
                                  unsigned *__restrict__ tile_count, unsigned *__restrict__ pair_slot,
                                  const unsigned *__restrict__ tile_start, unsigned *__restrict__ bins,
                                  unsigned *__restrict__ bin_pair, unsigned *__restrict__ big_list,
-                                 DevCounters *counters, int nsmall) {
+                                 unsigned *__restrict__ overflow_list, DevCounters *counters, int nsmall) {
     if (FILL && (int)blockIdx.x >= nsmall) {
         // workgroups past the triangles' own: the listed large triangles, a
         // workgroup each (their list is complete after the count pass)
@@ -379,7 +379,10 @@ __global__ void bin_small_kernel(const ViewConst *__restrict__ views, const TriS
     if (i < ntri) {
         a = pair_off[i];
         b = pair_off[i + 1];
-        if (b > capacity) b = a;                           // overflow path
+        if (b > capacity) {                                // overflow path (listed by the count pass)
+            if (!FILL && b > a) overflow_list[atomicAdd(&counters->overflow_list_len, 1u)] = (unsigned)i;
+            b = a;
+        }
         if (b - a > kBigBin) {
             if (!FILL) big_list[atomicAdd(&counters->big_bin_len, 1u)] = (unsigned)i;
             b = a;
@@ -429,17 +432,6 @@ __global__ void bin_big_kernel(const ViewConst *__restrict__ views, const TriSet
     }
 }
 
-
-__global__ void overflow_list_kernel(const unsigned *__restrict__ pair_off, int ntri, unsigned capacity,
-                                     unsigned *__restrict__ list, DevCounters *counters) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntri) return;
-    const bool of = pair_off[i + 1] > pair_off[i] && pair_off[i + 1] > capacity;
-    if (of) {
-        const unsigned slot = atomicAdd(&counters->overflow_list_len, 1u);
-        list[slot] = (unsigned)i;
-    }
-}
 
 // ----------------------------------------------------------------------------- raster
 
@@ -635,17 +627,17 @@ hipError_t launch_setup(const ViewConst *views, int nviews, int max_faces, const
 hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const unsigned *pair_off, int ntri,
                           unsigned capacity, int tile, unsigned *tile_count, unsigned *tile_start,
                           unsigned *pair_slot, unsigned *scan_scratch, int ntiles, unsigned *bins,
-                          unsigned *bin_pair, unsigned *overflow_list, DevCounters *counters, hipStream_t s) {
-    // the list of large triangles lives in overflow_list until the overflow list is built below
+                          unsigned *bin_pair, unsigned *overflow_list, unsigned *big_list, DevCounters *counters,
+                          hipStream_t s) {
     const dim3 tgrid((ntri + 255) / 256);
     const dim3 bgrid(1024);
     if (ntri > 0) {
         hipLaunchKernelGGL(bin_small_kernel<false>, tgrid, dim3(256), 0, s, views, setup, pair_off, ntri, capacity, tile,
                            tile_count, pair_slot, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
-                           overflow_list, counters, (int)tgrid.x);
+                           big_list, overflow_list, counters, (int)tgrid.x);
         hipLaunchKernelGGL(bin_big_kernel<false>, bgrid, dim3(256), 0, s, views, setup, pair_off, tile, tile_count,
                            pair_slot, (const unsigned *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr,
-                           (const unsigned *)overflow_list, (const DevCounters *)counters);
+                           (const unsigned *)big_list, (const DevCounters *)counters);
     }
     hipError_t e = launch_scan(tile_count, tile_start, scan_scratch, ntiles, s);
     if (e != hipSuccess) return e;
@@ -653,11 +645,8 @@ hipError_t launch_binning(const ViewConst *views, const TriSetup *setup, const u
         // the fill pass and the large triangles' fill in one launch (bgrid.x extra workgroups)
         hipLaunchKernelGGL(bin_small_kernel<true>, dim3(tgrid.x + bgrid.x), dim3(256), 0, s, views, setup, pair_off,
                            ntri, capacity, tile, (unsigned *)nullptr, pair_slot, (const unsigned *)tile_start, bins,
-                           bin_pair, overflow_list, counters, (int)tgrid.x);
+                           bin_pair, big_list, overflow_list, counters, (int)tgrid.x);
     }
-    if (ntri > 0)
-        hipLaunchKernelGGL(overflow_list_kernel, dim3((ntri + 255) / 256), dim3(256), 0, s, pair_off, ntri, capacity,
-                           overflow_list, counters);
     return hipGetLastError();
 }
 
