@@ -149,22 +149,6 @@ __global__ void light_maps_out_kernel(const float *src, int S, int sp, int P, bo
     out[(long long)S * S + t] = b;
 }
 
-// Two ranges cleared by one launch.
-__global__ void zero2_kernel(unsigned *p, size_t n, unsigned *q, size_t m) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += (size_t)gridDim.x * blockDim.x) {
-        if (i < n) p[i] = 0u;
-        else q[i - n] = 0u;
-    }
-}
-
-hipError_t zero2_async(void *p, size_t bytes_p, void *q, size_t bytes_q, hipStream_t s) {
-    const size_t n = bytes_p / 4, m = bytes_q / 4;
-    if (n + m == 0) return hipSuccess;
-    const size_t blocks = std::min<size_t>((n + m + 255) / 256, 4096);
-    hipLaunchKernelGGL(zero2_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned *)p, n, (unsigned *)q, m);
-    return hipGetLastError();
-}
-
 hipError_t zero_async(void *p, size_t bytes, hipStream_t s) {
     const size_t n = bytes / 4;
     if (n == 0) return hipSuccess;
@@ -720,9 +704,9 @@ dsm_status enqueue_forward(dsm_plan *p, const float *verts, const float *lparams
     float *img0 = at<float>(saved, p->sv_img0);
 
     DSM_MARK(DSM_STAGE_SETUP);
-    // counters (saved) and tile counts (scratch)
-    DSM_TRY(zero2_async(saved, p->sv_zero_end, scratch, p->sc_zero_fwd_end, s));
-    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, at<float>(saved, p->sv_zc), s));
+    // with the light frames, the counters (saved) and the tile counts (scratch) are cleared
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, nullptr, at<float>(saved, p->sv_zc), saved,
+                                p->sv_zero_end, scratch, p->sc_zero_fwd_end, s));
     DSM_TRY(launch_transform(p->views_d, p->nviews, p->max_verts, verts, clip, s));
     DSM_TRY(launch_tri_verts(p->scene_vert_off_d, p->scene_face_off_d, p->B, p->max_scene_faces, p->faces_d, verts,
                              albedo, p->C, tv, s));
@@ -789,12 +773,12 @@ dsm_status enqueue_backward(dsm_plan *p, const float *verts, const float *lparam
     float *jac = at<float>(scratch, p->sc_jac);
 
     DSM_MARK(DSM_STAGE_BWD_SETUP);
-    // big count, zero corner record, gM, silhouette gclip; and the pair flags (the 8x8 tile
-    // walks set only the flags of pairs that got a sum)
-    DSM_TRY(zero2_async(big_count, p->sc_zero_bwd_end - p->sc_bigcount, pair_flag,
-                        ((size_t)p->capacity + 3) & ~(size_t)3, s));
+    // with the light frames and their Jacobian: big count, zero corner record, gM, silhouette
+    // gclip; and the pair flags (the 8x8 tile walks set only the flags of pairs that got a sum)
+    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, jac, nullptr, big_count,
+                                p->sc_zero_bwd_end - p->sc_bigcount, pair_flag, ((size_t)p->capacity + 3) & ~(size_t)3,
+                                s));
     DSM_TRY(launch_overflow_rows_zero(overflow, cnt, gtri, s));
-    DSM_TRY(launch_light_frames(p->views_d, p->light_cams_d, lparams, p->L, jac, nullptr, s));
     DSM_MARK(DSM_STAGE_CAMERA_AA_ADJ);
     DSM_TRY(launch_aa_camera_backward(p->views_d, p->renders_d, p->R, p->max_cam_pix, setup, p->faces_d, silm,
                                       verts, keys, aa_flag, img0, gimg, gimg0, gclip, p->C, s));

@@ -282,8 +282,9 @@ bool valid_filter(int S, int filter, int k);
 struct CamStatic;
 // Jacobian of a light frame (M[16], pos[3], dir[3]) w.r.t. its three parameter components, [22][3].
 constexpr int kJac = 66;
+// Also clears bytes1 at z1 and bytes2 at z2 (multiples of 4) in the same launch.
 hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
-                               float *zc_out, hipStream_t s);
+                               float *zc_out, void *z1, size_t bytes1, void *z2, size_t bytes2, hipStream_t s);
 hipError_t launch_transform(const ViewConst *views, int nviews, int max_verts, const float *verts, float4 *clip,
                             hipStream_t s);
 hipError_t launch_silhouettes(const ViewConst *views, int nviews, int max_faces, const int *adj,

@@ -48,9 +48,20 @@ __device__ void light_jacobian(const CamStatic &cam, const float *param, float *
 
 // One thread per light: the light camera from its float32 parameter, in
 // float64, rounded to float32 for the rest of the pipeline; with jac, also
-// the frame's Jacobian (one launch for both).
+// the frame's Jacobian.  Workgroups from nf on clear the words z1[0, n1) and
+// z2[0, n2) instead (the pass's counters and accumulators: one launch for
+// all of it).
 __global__ void light_frames_kernel(ViewConst *views, const CamStatic *cams, const float *params, int L,
-                                    float *zc_out, float *jac) {
+                                    float *zc_out, float *jac, int nf, unsigned *z1, size_t n1, unsigned *z2,
+                                    size_t n2) {
+    if ((int)blockIdx.x >= nf) {
+        const size_t stride = (size_t)(gridDim.x - nf) * blockDim.x;
+        for (size_t i = (size_t)(blockIdx.x - nf) * blockDim.x + threadIdx.x; i < n1 + n2; i += stride) {
+            if (i < n1) z1[i] = 0u;
+            else z2[i - n1] = 0u;
+        }
+        return;
+    }
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L) return;
     const double p[3] = {params[3 * l], params[3 * l + 1], params[3 * l + 2]};
@@ -594,10 +605,13 @@ __global__ void overflow_raster_kernel(const ViewConst *__restrict__ views, cons
 // ----------------------------------------------------------------------------- host launchers
 
 hipError_t launch_light_frames(ViewConst *views, const CamStatic *cams, const float *params, int L, float *jac,
-                               float *zc_out, hipStream_t s) {
-    if (L == 0) return hipSuccess;
-    hipLaunchKernelGGL(light_frames_kernel, dim3((L + 63) / 64), dim3(64), 0, s, views, cams, params, L, zc_out,
-                       jac);
+                               float *zc_out, void *z1, size_t bytes1, void *z2, size_t bytes2, hipStream_t s) {
+    const int nf = (L + 63) / 64;
+    const size_t n1 = bytes1 / 4, n2 = bytes2 / 4;
+    const size_t nz = std::min<size_t>((n1 + n2 + 255) / 256, 16384);
+    if (nf + nz == 0) return hipSuccess;
+    hipLaunchKernelGGL(light_frames_kernel, dim3((unsigned)(nf + nz)), dim3(64), 0, s, views, cams, params, L, zc_out,
+                       jac, nf, (unsigned *)z1, n1, (unsigned *)z2, n2);
     return hipGetLastError();
 }
 
