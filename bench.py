@@ -50,10 +50,10 @@ HBM_PEAK_GBS = 8000.0
 # had when the counters were taken (and at tile side 8, where they were).
 PMC_COPY = dict(fetch_kib=65547.6, write_kib=131072.0, moved_kib=131072.0)
 PMC = {
-    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=65751.2, write_kib=131072.0, rd_bytes=134560218, wr_bytes=134217728, waves=32768, valu_per_wave=716.2, valu_busy=0.589, occupancy=19.3, sources=('blur.hip', 'dsm_internal.h'), sha1='890107d45ce20dd2'),
-    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65622.1, write_kib=131072.0, rd_bytes=134309491, wr_bytes=134217728, waves=32768, valu_per_wave=943.1, valu_busy=0.803, occupancy=20.1, sources=('blur.hip', 'dsm_internal.h'), sha1='890107d45ce20dd2'),
-    'lookup': dict(kernel='lookup_kernel<2>', fetch_kib=200689.5, write_kib=65536.0, rd_bytes=410704218, wr_bytes=67108864, waves=131072, valu_per_wave=466.0, valu_busy=0.958, occupancy=26.2, sources=('shade.hip', 'dsm_internal.h'), sha1='6543688542ebd3ca'),
-    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=117285.4, write_kib=120145.0, rd_bytes=239956429, wr_bytes=123028627, waves=262144, valu_per_wave=854.4, valu_busy=0.764, occupancy=14.8, sources=('grad.hip', 'dsm_internal.h'), sha1='eb59cc09c08efaa1'),
+    'filter': dict(kernel='blur_kernel<false, 2, true>', fetch_kib=65751.8, write_kib=131072.0, rd_bytes=134574259, wr_bytes=134217728, waves=32768, valu_per_wave=716.2, valu_busy=0.585, occupancy=19.8, sources=('blur.hip', 'dsm_internal.h'), sha1='e7468a0f4ddb340f'),
+    'filter_adj': dict(kernel='blur_kernel<true, 2, true>', fetch_kib=65621.9, write_kib=131072.0, rd_bytes=134309030, wr_bytes=134217728, waves=32768, valu_per_wave=943.1, valu_busy=0.801, occupancy=20.1, sources=('blur.hip', 'dsm_internal.h'), sha1='e7468a0f4ddb340f'),
+    'lookup': dict(kernel='lookup_kernel<2>', fetch_kib=200689.8, write_kib=65536.0, rd_bytes=410704768, wr_bytes=67108864, waves=131072, valu_per_wave=466.0, valu_busy=0.952, occupancy=26.3, sources=('shade.hip', 'dsm_internal.h'), sha1='24a515cac17e6ff0'),
+    'lookup_adj': dict(kernel='lookup_backward_kernel_1l<8>', fetch_kib=117285.1, write_kib=120145.4, rd_bytes=239955072, wr_bytes=123028288, waves=262144, valu_per_wave=854.4, valu_busy=0.763, occupancy=14.8, sources=('grad.hip', 'dsm_internal.h'), sha1='8b4f6eb42447484f'),
 }
 
 # Issue peak of the vector ALUs: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per
